@@ -1,0 +1,110 @@
+"""Pins of the oracle's exchange energy (Eqs. EX, EX_ACE) and its orbital
+gradient:
+
+* three independent formulas agree: Parseval sum over pair densities,
+  1/2 Re tr M_occ, and -1/2 sum |<xi_k, phi_i>|^2
+* plane-wave closed form E_X = 1/2 sum_i lambda_i
+* homogeneity E_X(t phi) = t^4 E_X(phi)
+* gradient: PyTorch autograd of an FP64 energy written with torch.fft, and
+  exact 5-point finite differences (E_X is a quartic along any line)
+* golden values for the seeded 24^3 case, written by tests/golden/make_golden.py
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_07159_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("kind,mu,g0", [("coulomb", 0, 0), ("erfc", 0.4, 0), ("erfc", 0.4, 3.0)])
+def test_energy_three_ways(kind, mu, g0):
+    g = O.Grid.cubic(10, 6.0, kind, mu, g0)
+    psi = synth.smooth_orbitals(10, 6.0, 9, seed=21)
+    nocc = 6
+    phi = psi[:nocc]
+    W = O.build_W(phi, psi, g)
+    M, L, xi = O.compress(psi, W, g)
+    e1 = O.exchange_energy_direct(phi, g)
+    e2 = O.exchange_energy_trace(M, nocc)
+    e3 = O.exchange_energy_ace(phi, xi, g)
+    assert abs(e1 - e2) <= 1e-13 * abs(e1)
+    assert abs(e1 - e3) <= 1e-13 * abs(e1)
+    assert e1 < 0
+
+
+def test_energy_planewave_closed_form():
+    n, L = 8, 5.0
+    g = O.Grid.cubic(n, L, "erfc", 0.5, 1.0)
+    occ = [(0, 0, 0), (1, 2, 0), (-1, 0, 3), (2, 2, 2)]
+    phi = synth.planewave_orbitals(n, L, occ)
+    lam = O.planewave_exchange_eigs(occ, occ, g)
+    assert abs(O.exchange_energy_direct(phi, g) - 0.5 * lam.sum()) <= 1e-14 * abs(lam.sum())
+
+
+def test_energy_g0_shift_is_rank_nocc():
+    # K(0) = g0 adds -(g0/Omega) sum_i phi_i <phi_i, .> to V_X, so for orthonormal
+    # phi the energy shifts by exactly -g0 N_occ / (2 Omega)
+    g_a = O.Grid.cubic(8, 5.0)
+    g_b = O.Grid.cubic(8, 5.0, g0=2.0)
+    phi = synth.smooth_orbitals(8, 5.0, 5, seed=8)
+    d = O.exchange_energy_direct(phi, g_b) - O.exchange_energy_direct(phi, g_a)
+    assert abs(d - (-2.0 * 5 / (2 * g_a.omega))) <= 1e-13
+
+
+def test_energy_homogeneous_degree_four():
+    g = O.Grid.cubic(8, 5.0)
+    phi = synth.smooth_orbitals(8, 5.0, 4, seed=8)
+    e = O.exchange_energy_direct(phi, g)
+    assert abs(O.exchange_energy_direct(1.7 * phi, g) - 1.7 ** 4 * e) <= 1e-13 * abs(e) * 9
+
+
+def test_gradient_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    g = O.Grid.cubic(6, 4.0, "erfc", 0.8)
+    phi = synth.smooth_orbitals(6, 4.0, 3, seed=4, ecut=30.0)
+    K = torch.tensor(O.kernel_g(g))
+    x = torch.tensor(phi, requires_grad=True)
+
+    def energy(p):
+        rho = torch.conj(p)[:, None] * p[None, :]                 # [j, i]
+        rh = torch.fft.fftn(rho, dim=(2, 3, 4))
+        return -0.5 * g.dV / g.ng * torch.sum(K * (rh.real ** 2 + rh.imag ** 2))
+
+    e = energy(x)
+    e.backward()
+    e = e.detach()
+    assert abs(float(e) - O.exchange_energy_direct(phi, g)) <= 1e-14 * abs(float(e))
+    G = O.exchange_energy_grad(phi, g)
+    # PyTorch's gradient of a real loss w.r.t. a complex leaf is 2 dL/dz*
+    np.testing.assert_allclose(x.grad.numpy(), 2.0 * G, atol=1e-14 * np.abs(G).max() * 50)
+
+
+def test_gradient_exact_five_point_stencil():
+    g = O.Grid.cubic(8, 5.0)
+    phi = synth.smooth_orbitals(8, 5.0, 4, seed=10)
+    G = O.exchange_energy_grad(phi, g)
+    D = synth.random_directions(phi.shape, 3, seed=5, norm=np.linalg.norm(phi))
+    for d in D:
+        h = 1e-2
+        f = [O.exchange_energy_direct(phi + k * h * d, g) for k in (-2, -1, 1, 2)]
+        fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        # d/dt E(phi + t d) at 0 = 2 Re <dE/dphi*, d>  (plain sum, no dV)
+        an = 2.0 * np.real(np.vdot(G, d))
+        assert abs(fd - an) <= 1e-9 * max(abs(an), 1e-3)
+
+
+def test_golden_seeded_case():
+    with open(os.path.join(GOLDEN, "smooth24_seed0.json")) as f:
+        gold = json.load(f)
+    g = O.Grid.cubic(24, 10.0)
+    psi = synth.smooth_orbitals(24, 10.0, 8, seed=0)
+    e = O.exchange_energy_direct(psi, g)
+    assert abs(e - gold["E_X_coulomb"]) <= 1e-12 * abs(e)
+    ge = O.Grid.cubic(24, 10.0, "erfc", 0.106)
+    e2 = O.exchange_energy_direct(psi, ge)
+    assert abs(e2 - gold["E_X_erfc_mu0.106"]) <= 1e-12 * abs(e2)
