@@ -1,0 +1,267 @@
+"""Benchmark of the ACE build on one MI355X.
+
+One step = the whole hot path on one batch of orbitals:
+  orthonormalise psi (FP64 CholQR2) -> W = V_X[phi] psi (n_occ x n_band pair
+  Poisson solves) -> compress (M = <psi, W>, Cholesky, xi = W L^{-H}) ->
+  V_ACE psi (low-rank apply) -> E_X from xi.
+Default workload: 48^3 grid, cubic L = 20.5 bohr, N_occ = 64, N_band = 80,
+mixed precision (FP32 FFTs and apply, BF16-split M, FP64 Cholesky/TRSM).
+
+Prints ONE JSON line; metric value = pair Poisson solves per second of whole
+steps (N_occ * N_band pairs per step).  Inputs are synthetic smooth orthonormal
+orbitals (seeded), resident in HBM before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "cfg1": dict(n=24, L=10.0, nocc=8, nband=8, nx=8, kind="coulomb", mu=0.0, prec="fp64",
+                 desc="24^3 grid, L=10 bohr, N_occ=N_band=8, complex128, Coulomb"),
+    "cfg2": dict(n=48, L=20.5, nocc=64, nband=80, nx=80, kind="coulomb", mu=0.0, prec="mixed",
+                 desc="48^3 grid, L=20.5 bohr, N_occ=64, N_band=80, complex64 FFTs, "
+                      "BF16-split M, FP64 Cholesky/TRSM, Coulomb"),
+    "cfg3": dict(n=72, L=30.8, nocc=216, nband=256, nx=256, kind="erfc", mu=0.106, prec="fp32",
+                 desc="72^3 grid, L=30.8 bohr, N_occ=216, N_band=256, FP32 FFTs, FP64 "
+                      "compression, erfc mu=0.106"),
+}
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, seconds=10.0):
+    """Time the FP64 oracle's pair solves on a bounded sample of the workload:
+    whole columns j of W (each column = N_occ pair solves), as many as fit in
+    about `seconds` of single-threaded CPU work."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1601_07159_amd import synth
+    psi = synth.smooth_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
+    phi = psi[:cfg["nocc"]]
+    g = O.Grid.cubic(cfg["n"], cfg["L"], cfg["kind"], cfg["mu"])
+    t0 = time.perf_counter()
+    O.build_W(phi, psi, g, columns=[0])
+    t1 = time.perf_counter()
+    per_col = max(t1 - t0, 1e-6)
+    ncols = int(max(1, min(cfg["nband"] - 1, seconds / per_col)))
+    t0 = time.perf_counter()
+    O.build_W(phi, psi, g, columns=list(range(1, 1 + ncols)))
+    dt = time.perf_counter() - t0
+    pairs = ncols * cfg["nocc"]
+    return {"value": pairs / dt, "unit": "pair solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle build_W columns j=1..{ncols} ({pairs} pair solves, FP64 NumPy "
+                      f"pocketfft, single thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain copy of known size (for counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1601_07159_amd import ace, synth
+
+    cfg = dict(WORKLOADS[args.workload])
+    if args.prec:
+        cfg["prec"] = args.prec
+    prec = cfg["prec"]
+    n, L, nocc, nband, nx = cfg["n"], cfg["L"], cfg["nocc"], cfg["nband"], cfg["nx"]
+    grid = ace.Grid.cubic(n, L, cfg["kind"], cfg["mu"])
+    ng = grid.ng
+    cdt = torch.complex128 if prec == "fp64" else torch.complex64
+    sbytes = 16 if prec == "fp64" else 8
+
+    log(f"bench: workload {args.workload} prec={prec}: generating inputs")
+    psi_np = synth.smooth_orbitals(n, L, nband, seed=0)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    psi_in = torch.from_numpy(psi_np).to(dev, cdt)
+
+    ctx = ace.Context(0)
+    ctx.reserve(grid, prec, nocc, nband, nx)
+
+    def make_bufs(dt):
+        return dict(Q=torch.empty((nband, ng), dtype=dt, device=dev),
+                    W=torch.empty((nband, ng), dtype=dt, device=dev),
+                    xi=torch.empty((nband, ng), dtype=dt, device=dev),
+                    Y=torch.empty((nx, ng), dtype=dt, device=dev),
+                    e=torch.empty((), dtype=torch.float64, device=dev),
+                    info=torch.zeros(1, dtype=torch.int32, device=dev))
+
+    bufs = make_bufs(cdt)
+    X_in = psi_in.reshape(nband, ng)[:nx]
+
+    stage_ev = []
+
+    def step(p, b, src, timed=False):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timed else None
+        if timed:
+            evs[0].record()
+        ctx.orthonormalize(src.reshape(nband, ng), grid, p, info=b["info"], out=b["Q"])
+        if timed:
+            evs[1].record()
+        ctx.build_W(b["Q"][:nocc], b["Q"], grid, p, out=b["W"])
+        if timed:
+            evs[2].record()
+        ctx.compress(b["Q"], b["W"], grid, p, info=b["info"], out=b["xi"])
+        if timed:
+            evs[3].record()
+        ctx.apply(b["xi"], b["Q"][:nx], grid, p, out=b["Y"])
+        if timed:
+            evs[4].record()
+        ctx.exchange_energy(b["Q"][:nocc], grid, p, xi=b["xi"], out=b["e"])
+        if timed:
+            evs[5].record()
+            stage_ev.append(evs)
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step(prec, bufs, psi_in)
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} steps")
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(prec, bufs, psi_in, timed=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = ctx.profile_report()
+    ctx.profile(False)
+    ms_step = wall * 1e3 / args.steps
+    stages = ["orthonormalize", "build_W", "compress", "apply", "energy"]
+    st_ms = {s: float(np.mean([ev[k].elapsed_time(ev[k + 1]) for ev in stage_ev]))
+             for k, s in enumerate(stages)}
+    pairs = nocc * nband
+    value = pairs * args.steps / wall
+    log(f"bench: {ms_step:.3f} ms/step, stages {st_ms}")
+
+    # dominant FFT-pass kernel and its roofline
+    fft_kernels = {"pair_fwd_slab": 3, "pencil_kernel": 2, "inv_slab_accum": 1}
+    dom = max(fft_kernels, key=lambda k: prof.get(k, {"ms": 0})["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / d["launches"]
+    pairs_per_launch = pairs * args.steps / d["launches"]
+    # algorithmic HBM bytes per pair for each pass:
+    #   forward slab: write N_g s (inputs amortised over the pair block, not counted)
+    #   pencil: read + write N_g s
+    #   inverse slab: read N_g s (phi and W amortised over the block, not counted)
+    bytes_per_pair = {"pair_fwd_slab": 1, "pencil_kernel": 2, "inv_slab_accum": 1}[dom] * ng * sbytes
+    achieved = bytes_per_pair * pairs_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(avg_ms, 4),
+                "pairs_per_launch": pairs_per_launch}
+    build_ms = st_ms["build_W"]
+    build_bytes = 4 * ng * sbytes * pairs
+    extra = {
+        "stage_ms": {k: round(v, 4) for k, v in st_ms.items()},
+        "build_pairs_per_s": pairs / (build_ms * 1e-3),
+        "build_fft_algorithmic_GBs": build_bytes / (build_ms * 1e-3) / 1e9,
+        "apply_tflops": 16.0 * ng * nband * nx / (st_ms["apply"] * 1e-3) / 1e12,
+        "per_kernel": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 5)}
+                       for k, v in prof.items()},
+    }
+
+    # errors vs an FP64 run on the same seed (outside the timed region)
+    if not args.no_fp64 and prec != "fp64":
+        log("bench: FP64 comparison run")
+        b64 = make_bufs(torch.complex128)
+        psi64 = torch.from_numpy(psi_np).to(dev, torch.complex128)
+        step("fp64", b64, psi64)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(max(2, min(args.steps, 5))):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step("fp64", b64, psi64)
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        extra["fp64_ms_per_step"] = float(np.median(t))
+        stage_ev.clear()
+        step("fp64", b64, psi64, timed=True)
+        torch.cuda.synchronize()
+        ev = stage_ev[-1]
+        extra["fp64_stage_ms"] = {s: round(ev[k].elapsed_time(ev[k + 1]), 4)
+                                  for k, s in enumerate(stages)}
+        extra["apply_tflops_fp64"] = 16.0 * ng * nband * nx / (
+            extra["fp64_stage_ms"]["apply"] * 1e-3) / 1e12
+
+        def relerr(a, b):
+            a = a.to(torch.complex128)
+            return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        extra["errors_vs_fp64"] = {
+            "W": relerr(bufs["W"], b64["W"]),
+            "xi": relerr(bufs["xi"], b64["xi"]),
+            "V_ACE_psi": relerr(bufs["Y"], b64["Y"]),
+            "E_X": abs(float(bufs["e"]) - float(b64["e"])) / abs(float(b64["e"])),
+            "E_X_fp64": float(b64["e"]),
+        }
+        del b64, psi64
+
+    if args.copy_probe:
+        src = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["copy_probe_bytes"] = 2 * src.numel() * 8
+
+    out = {
+        "metric": "pair Poisson solves/s (whole ACE build step)",
+        "value": round(value, 1),
+        "unit": "pair solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16split"}[prec],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {cfg['desc']}", "precision": prec,
+                   "grid": n, "L_bohr": L, "n_occ": nocc, "n_band": nband, "n_x": nx,
+                   "pairs_per_step": pairs, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

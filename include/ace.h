@@ -1,0 +1,177 @@
+/*
+ * libace: the adaptively compressed exchange (ACE) build on one AMD Instinct
+ * MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * Method: L. Lin, "Adaptively Compressed Exchange Operator",
+ * J. Chem. Theory Comput. 12, 2242 (2016).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.   A periodic orthorhombic cell with edges L[0..2] (bohr) sampled on
+ *         n[0] x n[1] x n[2] points (this release: n[0] = n[1] = n[2], a value
+ *         listed by ace_supported_n).  N_g = n0 n1 n2, Omega = L0 L1 L2,
+ *         dV = Omega / N_g.
+ * Orbitals.  Device arrays of complex numbers with interleaved (re, im)
+ *         parts: complex128 (two doubles) when prec == ACE_FP64, complex64
+ *         (two floats) for ACE_FP32 and ACE_MIXED.  A block of N orbitals is
+ *         orbital-major: orbital b starts at element b * ld (ld >= N_g, in
+ *         complex elements) and holds its N_g grid values in C order
+ *         (index (x0 * n1 + x1) * n2 + x2).  This is an N_g x N column-major
+ *         matrix with leading dimension ld.
+ * Inner product.  <f, g> = dV * sum_r conj(f(r)) g(r); orbitals are expected
+ *         to satisfy <phi_i, phi_j> = delta_ij where the paper says so.
+ * Ownership.  The caller owns every pointer passed in; the library never frees
+ *         or retains them beyond the call.  The context owns its workspace.
+ * Execution.  Every call is asynchronous and ordered on the context's HIP
+ *         stream; outputs are valid once that stream reaches the call.  The
+ *         only calls that may synchronise are those documented to do so.
+ * Errors.  Argument errors are detected before any work is enqueued and return
+ *         ACE_E_ARG or ACE_E_UNSUPPORTED with nothing written.  HIP runtime
+ *         failures return ACE_E_HIP; ace_last_error() gives the text.
+ *         Calls on one context must not overlap from several host threads.
+ */
+#ifndef ACE_H
+#define ACE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ace_ctx_s* ace_ctx;
+
+typedef enum {
+  ACE_OK = 0,
+  ACE_E_ARG = 1,          /* invalid argument (null pointer, ld < N_g, sizes) */
+  ACE_E_NOT_PD = 2,       /* -M (or the Gram matrix) is not positive definite */
+  ACE_E_NOMEM = 3,        /* device workspace allocation failed */
+  ACE_E_HIP = 4,          /* a HIP runtime call failed */
+  ACE_E_UNSUPPORTED = 5   /* grid shape or precision not built into the library */
+} ace_status;
+
+typedef enum {
+  ACE_FP64 = 0,   /* complex128 data; FFTs, products and factorisations in FP64 */
+  ACE_FP32 = 1,   /* complex64 data; FFTs and apply in FP32; M, Cholesky, xi in FP64 */
+  ACE_MIXED = 2   /* complex64 data; FFTs and apply in FP32; M by BF16-split MFMA
+                     products with FP32 accumulation; Cholesky and xi in FP64 */
+} ace_prec;
+
+typedef enum {
+  ACE_COULOMB = 0, /* v(r) = 1/r, Fourier kernel 4 pi / |G|^2 (Section 2, Eq. VXkernel) */
+  ACE_ERFC = 1     /* v(r) = erfc(mu r)/r, kernel 4 pi/|G|^2 (1 - exp(-|G|^2/(4 mu^2)))
+                      (Section 2, Eq. EXSR: the short-range screened exchange) */
+} ace_kernel;
+
+typedef struct {
+  int n[3];      /* grid points per axis, n[0] slowest */
+  double L[3];   /* cell edges in bohr */
+  int kind;      /* ace_kernel */
+  double mu;     /* screening parameter (bohr^-1) for ACE_ERFC, ignored otherwise */
+  double g0;     /* kernel value used at G = 0, where 4 pi/|G|^2 is undefined; 0 removes
+                    the G = 0 component */
+} ace_grid;
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL
+ * means the default stream).  The context allocates device workspace lazily on
+ * the device current at creation. */
+ace_status ace_create(ace_ctx* out, void* hip_stream);
+ace_status ace_destroy(ace_ctx ctx);
+/* Rebind the stream used by later calls. */
+ace_status ace_set_stream(ace_ctx ctx, void* hip_stream);
+
+/* Grow the context workspace now so that later calls with at most these sizes
+ * allocate nothing.  Optional. */
+ace_status ace_reserve(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                       int max_nocc, int max_nband, int max_nx);
+
+/*
+ * W = scale * V_X[phi] psi                      (Section 2, Eq. applyVX2; Section 3, Eq. W)
+ *
+ * For every band j < n_band:
+ *   W_j(r) = -scale * sum_{i < n_occ} phi_i(r) u_ij(r),
+ *   u_ij   = ifftn( K(G) * fftn( conj(phi_i) * psi_j ) ),
+ * i.e. n_occ * n_band pair Poisson solves, each a 3-D FFT of the pair charge,
+ * a multiply by the kernel K(G) of the grid, an inverse 3-D FFT (1/N_g
+ * included) and an accumulation into w_j.  phi are the n_occ orbitals that
+ * define the exchange operator; psi the n_band >= 1 vectors it is applied to
+ * (psi = phi gives Eq. W; n_band > n_occ is the oversampled build at the end of
+ * Section 3).  scale = 1 is the Fock exchange; 1/4 the PBE0/HSE fraction.
+ * W must not overlap phi or psi.  ld_* >= N_g.
+ */
+ace_status ace_build_W(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                       const void* phi, int n_occ, long ld_phi,
+                       const void* psi, int n_band, long ld_psi,
+                       void* W, long ld_W, double scale);
+
+/*
+ * Compression (Section 3, Eqs. ACEconstruct2, Wtilde, ACE):
+ *   M = dV * psi^H W  (n_band x n_band), symmetrised M <- (M + M^H)/2,
+ *   -M = L L^H with L lower triangular, positive real diagonal,
+ *   xi = W L^{-H}     (n_band projection vectors, same layout as W).
+ * Afterwards V_ACE = -xi xi^H reproduces W on span(psi).
+ * L_out (nullable): n_band x n_band complex128, column-major, device memory;
+ *   receives L.
+ * info_dev (nullable): device int; receives 0 on success or k >= 1, the first
+ *   non-positive pivot (LAPACK potrf convention); xi is then unspecified.
+ *   When info_dev is NULL the call synchronises the stream and returns
+ *   ACE_E_NOT_PD on failure.
+ * xi must not overlap psi or W.
+ */
+ace_status ace_compress(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                        const void* psi, long ld_psi, const void* W, long ld_W,
+                        int n_band, void* xi, long ld_xi,
+                        void* L_out, int* info_dev);
+
+/*
+ * Y = V_ACE X = -xi (dV xi^H X)                  (Section 3, Eq. ACE)
+ * xi: n_band projection vectors; X, Y: n_x orbitals.  Y must not overlap xi or X.
+ */
+ace_status ace_apply(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                     const void* xi, int n_band, long ld_xi,
+                     const void* X, int n_x, long ld_x, void* Y, long ld_y);
+
+/*
+ * Fock exchange energy of the n_occ orbitals phi, written to *ex_dev (one
+ * device double).
+ *  xi != NULL: E_X = -1/2 sum_{i,k} |<xi_k, phi_i>|^2   (Eq. EX_ACE, no Poisson solve)
+ *  xi == NULL: E_X = -1/2 sum_{i,j} <rho_ji, v * rho_ji>, rho_ji = conj(phi_j) phi_i
+ *              (Eq. EX), by forward FFTs of the pairs i <= j and Parseval.
+ */
+ace_status ace_exchange_energy(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                               const void* phi, int n_occ, long ld_phi,
+                               const void* xi, int n_band, long ld_xi,
+                               double* ex_dev);
+
+/*
+ * Orthonormalise n vectors: Q = X R^{-1} with <Q_a, Q_b> = delta_ab and R upper
+ * triangular with positive real diagonal (the constraint of Eq. HF).  Computed
+ * as two rounds of Cholesky QR in FP64 (Gram matrix, Cholesky, triangular
+ * solve).  Q must not overlap X.  info_dev as in ace_compress.
+ */
+ace_status ace_orthonormalize(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                              const void* X, int n, long ld_x, void* Q, long ld_q,
+                              int* info_dev);
+
+/* Grid sizes n (per axis) compiled into this library; returns how many were
+ * written (at most cap). */
+int ace_supported_n(int* out, int cap);
+
+/* Per-kernel timing: when enabled every kernel launch is bracketed by HIP
+ * events on the context stream.  ace_profile_get synchronises the stream and
+ * reports, for entry idx, the kernel name, launch count and total time. */
+ace_status ace_profile_enable(ace_ctx ctx, int on);
+ace_status ace_profile_reset(ace_ctx ctx);
+int ace_profile_count(ace_ctx ctx);
+ace_status ace_profile_get(ace_ctx ctx, int idx, const char** name, long* launches,
+                           double* total_ms);
+
+/* Tuning knob: device bytes the build may use for in-flight pair spectra
+ * (the FFT intermediates of a block of pairs).  0 restores the default. */
+ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
+
+const char* ace_status_string(ace_status s);
+const char* ace_last_error(ace_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACE_H */

@@ -1,0 +1,72 @@
+"""ctypes declarations of libace's C ABI (include/ace.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libace.so")
+
+ACE_OK, ACE_E_ARG, ACE_E_NOT_PD, ACE_E_NOMEM, ACE_E_HIP, ACE_E_UNSUPPORTED = range(6)
+ACE_FP64, ACE_FP32, ACE_MIXED = 0, 1, 2
+ACE_COULOMB, ACE_ERFC = 0, 1
+
+EXPORTED = [
+    "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
+    "ace_apply", "ace_exchange_energy", "ace_orthonormalize", "ace_supported_n",
+    "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
+    "ace_set_pair_budget", "ace_status_string", "ace_last_error",
+]
+
+
+class AceGrid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3), ("kind", ctypes.c_int),
+                ("mu", ctypes.c_double), ("g0", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_l = ctypes.c_long
+_d = ctypes.c_double
+_gp = ctypes.POINTER(AceGrid)
+
+_PROTOS = {
+    "ace_create": (_i, [ctypes.POINTER(_vp), _vp]),
+    "ace_destroy": (_i, [_vp]),
+    "ace_set_stream": (_i, [_vp, _vp]),
+    "ace_reserve": (_i, [_vp, _gp, _i, _i, _i, _i]),
+    "ace_build_W": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l, _d]),
+    "ace_compress": (_i, [_vp, _gp, _i, _vp, _l, _vp, _l, _i, _vp, _l, _vp, _vp]),
+    "ace_apply": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l]),
+    "ace_exchange_energy": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp]),
+    "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),
+    "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
+    "ace_profile_enable": (_i, [_vp, _i]),
+    "ace_profile_reset": (_i, [_vp]),
+    "ace_profile_count": (_i, [_vp]),
+    "ace_profile_get": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_l),
+                             ctypes.POINTER(_d)]),
+    "ace_set_pair_budget": (_i, [_vp, _l]),
+    "ace_status_string": (ctypes.c_char_p, [_i]),
+    "ace_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library; raises if it has not been built (there is no
+    fallback implementation)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libace.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_1601_07159_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _PROTOS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,115 @@
+// Host-side internals of libace shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ace.h"
+#include "fft_core.h"
+
+struct ace_ctx_s {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_used = 0;
+  size_t pair_budget = 0;  // 0 = default
+  std::string last_error;
+  // profiling
+  bool profiling = false;
+  struct ProfEntry {
+    std::string name;
+    long launches = 0;
+    double ms = 0.0;
+  };
+  std::vector<ProfEntry> prof;
+  struct Pending {
+    int entry;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+};
+
+namespace ace {
+
+// Supported grid sizes per axis (cubic grids).  Each needs a radix plan in
+// fft_core.h and instantiations in fft_passes.hip.
+#define ACE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(40) X(48) X(64) X(72)
+
+ace_status fail(ace_ctx c, ace_status s, const std::string& msg);
+ace_status hip_fail(ace_ctx c, hipError_t e, const char* where);
+
+// Context workspace, a bump allocator over one device buffer.  Each entry
+// point first calls ws_begin with the total it will carve (the buffer grows if
+// needed, which synchronises the device; nothing is carved yet at that point),
+// then ws_take hands out 256-byte aligned pieces.  ws_take returns nullptr and
+// sets *st if a piece exceeds what ws_begin reserved.
+ace_status ws_begin(ace_ctx c, size_t total_bytes);
+void* ws_take(ace_ctx c, size_t bytes, ace_status* st);
+// Scratch bytes gemm_cn takes from the workspace for these sizes.
+size_t gemm_cn_scratch_bytes(int na, int nb, long K);
+
+// Profiling hooks around one launch.
+void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0);
+void prof_end(ace_ctx c, int entry, hipEvent_t e0);
+
+template <typename... KArgs, typename... Args>
+ace_status launch(ace_ctx c, const char* name, void (*kern)(KArgs...), dim3 grid, dim3 block,
+                  size_t shmem, Args... args) {
+  if (grid.x == 0 || grid.y == 0 || grid.z == 0) return ACE_OK;
+  int entry = -1;
+  hipEvent_t e0 = nullptr;
+  if (c->profiling) prof_begin(c, name, &entry, &e0);
+  hipLaunchKernelGGL(kern, grid, block, shmem, c->stream, static_cast<KArgs>(args)...);
+  hipError_t e = hipGetLastError();
+  if (c->profiling) prof_end(c, entry, e0);
+  if (e != hipSuccess) return hip_fail(c, e, name);
+  return ACE_OK;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct GridInfo {
+  int n;          // points per axis
+  long ng;        // n^3
+  double L[3];
+  int kind;
+  double mu, g0;
+  double omega, dV;
+};
+
+// Pair FFT stages (fft_passes.hip).
+template <typename T>
+ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
+                        const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale);
+template <typename T>
+ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
+                              long ldphi, double* ex_dev);
+
+// Dense stages (dense.hip).  Small matrices are complex128, column-major.
+// C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]
+template <typename T>
+ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
+                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split);
+// Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K)
+template <typename T>
+ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
+                   int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate);
+// In place: A (n x n, lower part) -> L with A = L L^H; info_dev gets 0 or the
+// failing pivot.  A nonzero *prior (nullable) is propagated instead.
+ace_status cholesky(ace_ctx c, cx<double>* A, int n, int* info_dev, const int* prior = nullptr);
+// Hermitian part of a square matrix scaled: A <- s * (A + A^H)/2
+ace_status hermitize(ace_ctx c, cx<double>* A, int n, double s);
+// Given L (lower), writes C = L^{-H} (upper) into C.
+ace_status tri_inv_herm(ace_ctx c, const cx<double>* L, int n, cx<double>* C, cx<double>* scratch,
+                        const int* info_dev);
+// *out = s * sum |A_ij|^2 over an m x n column-major block
+ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out);
+ace_status copy_matrix(ace_ctx c, const cx<double>* src, int n, cx<double>* dst);
+
+}  // namespace ace

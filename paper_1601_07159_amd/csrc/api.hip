@@ -1,0 +1,490 @@
+// C ABI of libace: argument validation, workspace, dispatch to the kernels.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ace_internal.h"
+
+#define ACE_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace ace {
+
+ace_status fail(ace_ctx c, ace_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+ace_status hip_fail(ace_ctx c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, ACE_E_HIP, m);
+}
+
+ace_status ws_begin(ace_ctx c, size_t total) {
+  c->ws_used = 0;
+  total = align_up(total ? total : 256, 256);
+  if (total <= c->ws_bytes) return ACE_OK;
+  if (c->ws) {
+    // queued kernels of earlier calls may still use the old buffer
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    if (e != hipSuccess) return hip_fail(c, e, "hipFree(workspace)");
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, total);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace allocation of %zu bytes failed", total);
+    return fail(c, ACE_E_NOMEM, buf);
+  }
+  c->ws = p;
+  c->ws_bytes = total;
+  return ACE_OK;
+}
+
+void* ws_take(ace_ctx c, size_t bytes, ace_status* st) {
+  bytes = align_up(bytes ? bytes : 256, 256);
+  if (c->ws_used + bytes > c->ws_bytes) {
+    *st = fail(c, ACE_E_NOMEM, "internal: workspace carve exceeds reservation");
+    return nullptr;
+  }
+  void* p = (char*)c->ws + c->ws_used;
+  c->ws_used += bytes;
+  return p;
+}
+
+void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0) {
+  int idx = -1;
+  for (size_t k = 0; k < c->prof.size(); ++k)
+    if (c->prof[k].name == name) idx = (int)k;
+  if (idx < 0) {
+    c->prof.push_back({name, 0, 0.0});
+    idx = (int)c->prof.size() - 1;
+  }
+  hipEvent_t e = nullptr;
+  if (!c->free_events.empty()) {
+    e = c->free_events.back();
+    c->free_events.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  if (e) hipEventRecord(e, c->stream);
+  *entry = idx;
+  *e0 = e;
+}
+
+void prof_end(ace_ctx c, int entry, hipEvent_t e0) {
+  if (!e0) return;
+  hipEvent_t e1 = nullptr;
+  if (!c->free_events.empty()) {
+    e1 = c->free_events.back();
+    c->free_events.pop_back();
+  } else if (hipEventCreate(&e1) != hipSuccess) {
+    c->free_events.push_back(e0);
+    return;
+  }
+  hipEventRecord(e1, c->stream);
+  c->pending.push_back({entry, e0, e1});
+}
+
+static void prof_collect(ace_ctx c) {
+  for (auto& p : c->pending) {
+    hipEventSynchronize(p.e1);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      c->prof[p.entry].ms += ms;
+      c->prof[p.entry].launches += 1;
+    }
+    c->free_events.push_back(p.e0);
+    c->free_events.push_back(p.e1);
+  }
+  c->pending.clear();
+}
+
+static bool grid_supported(int n) {
+  switch (n) {
+#define ACE_CASE(NV) \
+  case NV:           \
+    return true;
+    ACE_FOR_EACH_N(ACE_CASE)
+#undef ACE_CASE
+    default:
+      return false;
+  }
+}
+
+static ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out) {
+  if (!g) return fail(c, ACE_E_ARG, "grid is NULL");
+  if (prec != ACE_FP64 && prec != ACE_FP32 && prec != ACE_MIXED)
+    return fail(c, ACE_E_ARG, "unknown precision");
+  for (int a = 0; a < 3; ++a) {
+    if (g->n[a] <= 0) return fail(c, ACE_E_ARG, "grid size must be positive");
+    if (!(g->L[a] > 0.0) || !std::isfinite(g->L[a]))
+      return fail(c, ACE_E_ARG, "cell edges must be positive and finite");
+  }
+  if (g->kind != ACE_COULOMB && g->kind != ACE_ERFC) return fail(c, ACE_E_ARG, "unknown kernel");
+  if (g->kind == ACE_ERFC && !(g->mu > 0.0 && std::isfinite(g->mu)))
+    return fail(c, ACE_E_ARG, "screened kernel needs mu > 0");
+  if (!std::isfinite(g->g0)) return fail(c, ACE_E_ARG, "g0 must be finite");
+  if (g->n[0] != g->n[1] || g->n[1] != g->n[2] || !grid_supported(g->n[0]))
+    return fail(c, ACE_E_UNSUPPORTED, "grid must be cubic with n listed by ace_supported_n");
+  out->n = g->n[0];
+  out->ng = (long)g->n[0] * g->n[1] * g->n[2];
+  for (int a = 0; a < 3; ++a) out->L[a] = g->L[a];
+  out->kind = g->kind;
+  out->mu = g->mu;
+  out->g0 = g->g0;
+  out->omega = g->L[0] * g->L[1] * g->L[2];
+  out->dV = out->omega / (double)out->ng;
+  return ACE_OK;
+}
+
+static size_t elem_bytes(ace_prec p) { return p == ACE_FP64 ? 16 : 8; }
+
+struct Span {
+  const char* lo;
+  const char* hi;
+};
+static Span span_of(const void* p, int count, long ld, long ng, size_t eb) {
+  const char* b = (const char*)p;
+  return {b, b + ((size_t)(count - 1) * ld + ng) * eb};
+}
+static bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+
+static ace_status check_block(ace_ctx c, const void* p, int count, long ld, const GridInfo& g,
+                              const char* what) {
+  if (!p) return fail(c, ACE_E_ARG, std::string(what) + " is NULL");
+  if (count < 1) return fail(c, ACE_E_ARG, std::string(what) + ": count must be >= 1");
+  if (ld < g.ng) return fail(c, ACE_E_ARG, std::string(what) + ": ld < N_g");
+  return ACE_OK;
+}
+
+#define ACE_TRY(x)                   \
+  do {                               \
+    ace_status _s = (x);             \
+    if (_s != ACE_OK) return _s;     \
+  } while (0)
+
+// Cholesky failure reporting shared by compress and orthonormalize.
+static ace_status finish_info(ace_ctx c, int* info_ws, int* info_dev) {
+  if (info_dev) {
+    hipError_t e = hipMemcpyAsync(info_dev, info_ws, sizeof(int), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync(info)");
+    return ACE_OK;
+  }
+  int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, info_ws, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "info readback");
+  if (h != 0) {
+    char buf[96];
+    snprintf(buf, sizeof buf, "matrix not positive definite: pivot %d", h);
+    return fail(c, ACE_E_NOT_PD, buf);
+  }
+  return ACE_OK;
+}
+
+template <typename T>
+static ace_status compress_t(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
+                             const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
+                             cx<double>* L_out, int* info_dev, bool mixed) {
+  const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
+  ACE_TRY(ws_begin(c, 3 * mat + 256 + gemm_cn_scratch_bytes(nb, nb, g.ng)));
+  ace_status st = ACE_OK;
+  cx<double>* M = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* X = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
+  int* info = (int*)ws_take(c, 256, &st);
+  if (!M || !X || !C || !info) return st;
+  // M = dV psi^H W, then -M made exactly Hermitian
+  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed));
+  ACE_TRY(hermitize(c, M, nb, -1.0));
+  ACE_TRY(cholesky(c, M, nb, info));
+  if (L_out) ACE_TRY(copy_matrix(c, M, nb, L_out));
+  ACE_TRY(tri_inv_herm(c, M, nb, C, X, info));
+  ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true));
+  return finish_info(c, info, info_dev);
+}
+
+template <typename T>
+static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb, long ldxi,
+                          const cx<T>* X, int nx, long ldx, cx<T>* Y, long ldy) {
+  const size_t mat = align_up((size_t)nb * nx * sizeof(cx<double>), 256);
+  ACE_TRY(ws_begin(c, mat + gemm_cn_scratch_bytes(nb, nx, g.ng)));
+  ace_status st = ACE_OK;
+  cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
+  if (!C) return st;
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, X, ldx, nx, g.ng, -g.dV, C, nb, false));
+  return gemm_nn<T>(c, xi, ldxi, nb, C, nb, nx, Y, ldy, g.ng, false);
+}
+
+template <typename T>
+static ace_status energy_ace_t(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
+                               long ldphi, const cx<T>* xi, int nb, long ldxi, double* ex) {
+  const size_t mat = align_up((size_t)nb * nocc * sizeof(cx<double>), 256);
+  ACE_TRY(ws_begin(c, mat + gemm_cn_scratch_bytes(nb, nocc, g.ng)));
+  ace_status st = ACE_OK;
+  cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
+  if (!C) return st;
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, phi, ldphi, nocc, g.ng, g.dV, C, nb, false));
+  return sumsq(c, C, (long)nb * nocc, -0.5, ex);
+}
+
+template <typename T>
+static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, long ldx, cx<T>* Q,
+                         long ldq, int* info_dev) {
+  const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
+  const size_t tmp = align_up((size_t)n * g.ng * sizeof(cx<T>), 256);
+  ACE_TRY(ws_begin(c, 3 * mat + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, g.ng)));
+  ace_status st = ACE_OK;
+  cx<double>* S = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* Xs = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
+  int* info1 = (int*)ws_take(c, 256, &st);
+  int* info2 = (int*)ws_take(c, 256, &st);
+  cx<T>* Y = (cx<T>*)ws_take(c, tmp, &st);
+  if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
+  // round 1: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
+  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false));
+  ACE_TRY(hermitize(c, S, n, 1.0));
+  ACE_TRY(cholesky(c, S, n, info1));
+  ACE_TRY(tri_inv_herm(c, S, n, C, Xs, info1));
+  ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true));
+  // round 2 on Y restores orthogonality lost to rounding in round 1
+  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false));
+  ACE_TRY(hermitize(c, S, n, 1.0));
+  ACE_TRY(cholesky(c, S, n, info2, info1));
+  ACE_TRY(tri_inv_herm(c, S, n, C, Xs, info2));
+  ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true));
+  return finish_info(c, info2, info_dev);
+}
+
+}  // namespace ace
+
+using namespace ace;
+
+ACE_EXPORT const char* ace_status_string(ace_status s) {
+  switch (s) {
+    case ACE_OK: return "ok";
+    case ACE_E_ARG: return "invalid argument";
+    case ACE_E_NOT_PD: return "matrix not positive definite";
+    case ACE_E_NOMEM: return "out of device memory";
+    case ACE_E_HIP: return "HIP runtime error";
+    case ACE_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+ACE_EXPORT const char* ace_last_error(ace_ctx c) { return c ? c->last_error.c_str() : ""; }
+
+ACE_EXPORT int ace_supported_n(int* out, int cap) {
+  static const int list[] = {
+#define ACE_ITEM(NV) NV,
+      ACE_FOR_EACH_N(ACE_ITEM)
+#undef ACE_ITEM
+  };
+  const int count = (int)(sizeof(list) / sizeof(list[0]));
+  int k = 0;
+  for (; k < count && k < cap; ++k)
+    if (out) out[k] = list[k];
+  return out ? k : count;
+}
+
+ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream) {
+  if (!out) return ACE_E_ARG;
+  *out = nullptr;
+  ace_ctx c = new (std::nothrow) ace_ctx_s();
+  if (!c) return ACE_E_NOMEM;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return ACE_E_HIP;
+  }
+  *out = c;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
+  if (!c) return ACE_E_ARG;
+  if (c->ws) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->ws);
+  }
+  for (auto& p : c->pending) {
+    hipEventDestroy(p.e0);
+    hipEventDestroy(p.e1);
+  }
+  for (auto e : c->free_events) hipEventDestroy(e);
+  delete c;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_set_stream(ace_ctx c, void* stream) {
+  if (!c) return ACE_E_ARG;
+  c->stream = (hipStream_t)stream;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_set_pair_budget(ace_ctx c, long bytes) {
+  if (!c || bytes < 0) return ACE_E_ARG;
+  c->pair_budget = (size_t)bytes;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec, int max_nocc,
+                                  int max_nband, int max_nx) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  if (max_nocc < 1 || max_nband < 1 || max_nx < 0) return fail(c, ACE_E_ARG, "sizes");
+  const size_t eb = elem_bytes(prec);
+  const size_t pair_bytes = (size_t)g.ng * eb;
+  const size_t budget = c->pair_budget ? c->pair_budget : ((size_t)1 << 30);
+  size_t pairs = std::max<size_t>(1, budget / pair_bytes);
+  pairs = std::min<size_t>(pairs, (size_t)max_nocc * max_nband);
+  size_t need = align_up(pairs * pair_bytes, 256) + align_up((size_t)g.ng * 8, 256) +
+                align_up((size_t)max_nocc * (max_nocc + 1) / 2 * 4096 * 8, 256);
+  const int nmax = std::max(max_nband, std::max(max_nx, max_nocc));
+  need = std::max(need, 3 * align_up((size_t)nmax * nmax * 16, 256) + 512 +
+                            align_up((size_t)nmax * g.ng * eb, 256) +
+                            gemm_cn_scratch_bytes(nmax, nmax, g.ng));
+  return ws_begin(c, need);
+}
+
+ACE_EXPORT ace_status ace_build_W(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* phi,
+                                  int n_occ, long ld_phi, const void* psi, int n_band, long ld_psi,
+                                  void* W, long ld_W, double scale) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, phi, n_occ, ld_phi, g, "phi"));
+  ACE_TRY(check_block(c, psi, n_band, ld_psi, g, "psi"));
+  ACE_TRY(check_block(c, W, n_band, ld_W, g, "W"));
+  if (!std::isfinite(scale)) return fail(c, ACE_E_ARG, "scale must be finite");
+  const size_t eb = elem_bytes(prec);
+  const Span sw = span_of(W, n_band, ld_W, g.ng, eb);
+  if (overlap(sw, span_of(phi, n_occ, ld_phi, g.ng, eb)) ||
+      overlap(sw, span_of(psi, n_band, ld_psi, g.ng, eb)))
+    return fail(c, ACE_E_ARG, "W overlaps an input");
+  if (prec == ACE_FP64)
+    return build_W_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi,
+                                (const cx<double>*)psi, n_band, ld_psi, (cx<double>*)W, ld_W,
+                                scale);
+  return build_W_impl<float>(c, g, (const cx<float>*)phi, n_occ, ld_phi, (const cx<float>*)psi,
+                             n_band, ld_psi, (cx<float>*)W, ld_W, scale);
+}
+
+ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* psi,
+                                   long ld_psi, const void* W, long ld_W, int n_band, void* xi,
+                                   long ld_xi, void* L_out, int* info_dev) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, psi, n_band, ld_psi, g, "psi"));
+  ACE_TRY(check_block(c, W, n_band, ld_W, g, "W"));
+  ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
+  if (n_band > 4096) return fail(c, ACE_E_UNSUPPORTED, "n_band above 4096");
+  const size_t eb = elem_bytes(prec);
+  const Span sx = span_of(xi, n_band, ld_xi, g.ng, eb);
+  if (overlap(sx, span_of(psi, n_band, ld_psi, g.ng, eb)) ||
+      overlap(sx, span_of(W, n_band, ld_W, g.ng, eb)))
+    return fail(c, ACE_E_ARG, "xi overlaps an input");
+  if (prec == ACE_FP64)
+    return compress_t<double>(c, g, (const cx<double>*)psi, ld_psi, (const cx<double>*)W, ld_W,
+                              n_band, (cx<double>*)xi, ld_xi, (cx<double>*)L_out, info_dev, false);
+  return compress_t<float>(c, g, (const cx<float>*)psi, ld_psi, (const cx<float>*)W, ld_W, n_band,
+                           (cx<float>*)xi, ld_xi, (cx<double>*)L_out, info_dev,
+                           prec == ACE_MIXED);
+}
+
+ACE_EXPORT ace_status ace_apply(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* xi,
+                                int n_band, long ld_xi, const void* X, int n_x, long ld_x, void* Y,
+                                long ld_y) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
+  ACE_TRY(check_block(c, X, n_x, ld_x, g, "X"));
+  ACE_TRY(check_block(c, Y, n_x, ld_y, g, "Y"));
+  const size_t eb = elem_bytes(prec);
+  const Span sy = span_of(Y, n_x, ld_y, g.ng, eb);
+  if (overlap(sy, span_of(xi, n_band, ld_xi, g.ng, eb)) ||
+      overlap(sy, span_of(X, n_x, ld_x, g.ng, eb)))
+    return fail(c, ACE_E_ARG, "Y overlaps an input");
+  if (prec == ACE_FP64)
+    return apply_t<double>(c, g, (const cx<double>*)xi, n_band, ld_xi, (const cx<double>*)X, n_x,
+                           ld_x, (cx<double>*)Y, ld_y);
+  return apply_t<float>(c, g, (const cx<float>*)xi, n_band, ld_xi, (const cx<float>*)X, n_x, ld_x,
+                        (cx<float>*)Y, ld_y);
+}
+
+ACE_EXPORT ace_status ace_exchange_energy(ace_ctx c, const ace_grid* grid, ace_prec prec,
+                                          const void* phi, int n_occ, long ld_phi, const void* xi,
+                                          int n_band, long ld_xi, double* ex_dev) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, phi, n_occ, ld_phi, g, "phi"));
+  if (!ex_dev) return fail(c, ACE_E_ARG, "ex_dev is NULL");
+  if (xi) {
+    ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
+    if (prec == ACE_FP64)
+      return energy_ace_t<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi,
+                                  (const cx<double>*)xi, n_band, ld_xi, ex_dev);
+    return energy_ace_t<float>(c, g, (const cx<float>*)phi, n_occ, ld_phi, (const cx<float>*)xi,
+                               n_band, ld_xi, ex_dev);
+  }
+  if (prec == ACE_FP64)
+    return energy_direct_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi, ex_dev);
+  return energy_direct_impl<float>(c, g, (const cx<float>*)phi, n_occ, ld_phi, ex_dev);
+}
+
+ACE_EXPORT ace_status ace_orthonormalize(ace_ctx c, const ace_grid* grid, ace_prec prec,
+                                         const void* X, int n, long ld_x, void* Q, long ld_q,
+                                         int* info_dev) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, X, n, ld_x, g, "X"));
+  ACE_TRY(check_block(c, Q, n, ld_q, g, "Q"));
+  if (n > 4096) return fail(c, ACE_E_UNSUPPORTED, "n above 4096");
+  const size_t eb = elem_bytes(prec);
+  if (overlap(span_of(Q, n, ld_q, g.ng, eb), span_of(X, n, ld_x, g.ng, eb)))
+    return fail(c, ACE_E_ARG, "Q overlaps X");
+  if (prec == ACE_FP64)
+    return orth_t<double>(c, g, (const cx<double>*)X, n, ld_x, (cx<double>*)Q, ld_q, info_dev);
+  return orth_t<float>(c, g, (const cx<float>*)X, n, ld_x, (cx<float>*)Q, ld_q, info_dev);
+}
+
+ACE_EXPORT ace_status ace_profile_enable(ace_ctx c, int on) {
+  if (!c) return ACE_E_ARG;
+  c->profiling = on != 0;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_profile_reset(ace_ctx c) {
+  if (!c) return ACE_E_ARG;
+  prof_collect(c);
+  c->prof.clear();
+  return ACE_OK;
+}
+
+ACE_EXPORT int ace_profile_count(ace_ctx c) {
+  if (!c) return 0;
+  prof_collect(c);
+  return (int)c->prof.size();
+}
+
+ACE_EXPORT ace_status ace_profile_get(ace_ctx c, int idx, const char** name, long* launches,
+                                      double* total_ms) {
+  if (!c) return ACE_E_ARG;
+  prof_collect(c);
+  if (idx < 0 || idx >= (int)c->prof.size()) return ACE_E_ARG;
+  if (name) *name = c->prof[idx].name.c_str();
+  if (launches) *launches = c->prof[idx].launches;
+  if (total_ms) *total_ms = c->prof[idx].ms;
+  return ACE_OK;
+}

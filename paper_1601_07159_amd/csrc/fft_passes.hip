@@ -1,0 +1,355 @@
+// Pair Poisson solves of the exchange operator (Section 2, Eq. applyVX2;
+// Section 3, Eq. W): for every pair (i, j)
+//     u_ij = ifftn( K * fftn( conj(phi_i) psi_j ) ),   w_j += phi_i * u_ij.
+//
+// A 3-D FFT of an N^3 field does not fit on one compute unit, so each pair
+// crosses HBM three times:
+//   slab pass (forward)   one workgroup per (x0 slab, pair): the pair product is
+//                         formed while the slab is loaded, then 2-D FFT over
+//                         axes 2 and 1 in LDS; spectrum slab written out.
+//   pencil pass           one thread per (k1, k2) pencil along axis 0: forward
+//                         FFT, multiply by the scaled kernel, inverse FFT, all
+//                         in registers; lanes of a wave read consecutive
+//                         pencils, so every load is a contiguous 64-lane row.
+//   slab pass (inverse)   one workgroup per (x0 slab, band j): loops over the
+//                         occupied orbitals i of the block, inverse 2-D FFT of
+//                         u_ij, multiply by phi_i and accumulate into w_j,
+//                         which is written once per block (no atomics).
+// The 1/N_g of the inverse transform, the minus sign and the caller's scale are
+// folded into the kernel table K'(G) = -scale K(G) / N_g.
+#include <cmath>
+
+#include "ace_internal.h"
+
+namespace ace {
+
+namespace {
+
+constexpr double kFourPi = 12.566370614359172954;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n, double L0,
+                                                      double L1, double L2, int kind, double mu,
+                                                      double g0, double coef) {
+  const long ng = (long)n * n * n;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= ng) return;
+  const int k2 = (int)(idx % n);
+  const int k1 = (int)((idx / n) % n);
+  const int k0 = (int)(idx / ((long)n * n));
+  // integer frequency of FFT bin k (the Nyquist bin's sign does not matter: squared)
+  const int m0 = k0 <= n / 2 ? k0 : k0 - n;
+  const int m1 = k1 <= n / 2 ? k1 : k1 - n;
+  const int m2 = k2 <= n / 2 ? k2 : k2 - n;
+  const double twopi = 6.283185307179586477;
+  const double gx = twopi * m0 / L0, gy = twopi * m1 / L1, gz = twopi * m2 / L2;
+  const double g2 = gx * gx + gy * gy + gz * gz;
+  double K;
+  if (g2 > 0.0) {
+    K = kFourPi / g2;
+    if (kind == ACE_ERFC) K *= -expm1(-g2 / (4.0 * mu * mu));
+  } else {
+    K = g0;
+  }
+  Kt[idx] = T(coef * K);
+}
+
+// Pair of block-local index p.
+//  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
+//  mode 1: upper triangle i <= j, global triangle index p0 + p (row-major in j)
+__device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0, long p, int* i,
+                                        int* j) {
+  if (mode == 0) {
+    *i = i0 + (int)(p % A);
+    *j = j0 + (int)(p / A);
+  } else {
+    const long g = p0 + p;
+    long jj = (long)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
+    while (jj * (jj + 1) / 2 > g) --jj;
+    while ((jj + 1) * (jj + 2) / 2 <= g) ++jj;
+    *j = (int)jj;
+    *i = (int)(g - jj * (jj + 1) / 2);
+  }
+}
+
+// Forward slab pass: one workgroup of N threads per (x0, pair).
+template <int N, typename T>
+__global__ __launch_bounds__(N) void k_pair_fwd_slab(const cx<T>* __restrict__ phi, long ldphi,
+                                                     const cx<T>* __restrict__ psi, long ldpsi,
+                                                     cx<T>* __restrict__ buf, int mode, int i0,
+                                                     int A, int j0, long p0, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = N + 1;
+  __shared__ cx<T> s[N * LD];
+  const int x0 = blockIdx.x / npairs;
+  const int p = blockIdx.x - x0 * npairs;
+  int i, j;
+  pair_of(mode, i0, A, j0, p0, p, &i, &j);
+  const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
+  const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
+  const int t = threadIdx.x;
+#pragma unroll 4
+  for (int r = 0; r < N; ++r) s[r * LD + t] = cmulc(a[r * N + t], b[r * N + t]);
+  __syncthreads();
+  cx<T> v[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
+  fft_line<N, -1, T>(v);
+#pragma unroll
+  for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = s[q * LD + t];
+  fft_line<N, -1, T>(v);
+  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q * N + t] = v[q];
+}
+
+// Pencil pass: forward FFT along axis 0, multiply by K', inverse FFT.
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_pencil_kernel(cx<T>* __restrict__ buf,
+                                                      const T* __restrict__ Kt) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  const int p = blockIdx.x / TILES;
+  const int q = (blockIdx.x - p * TILES) * 64 + threadIdx.x;
+  if (q >= NN) return;
+  cx<T>* base = buf + (size_t)p * N * NN + q;
+  cx<T> v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = base[(size_t)k * NN];
+  fft_line<N, -1, T>(v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const T kk = Kt[k * NN + q];
+    v[k].x *= kk;
+    v[k].y *= kk;
+  }
+  fft_line<N, +1, T>(v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) base[(size_t)k * NN] = v[k];
+}
+
+// Inverse slab pass with the phi-multiply and accumulation over the i block.
+template <int N, typename T, bool ACC_LDS>
+__global__ __launch_bounds__(N) void k_inv_slab_accum(const cx<T>* __restrict__ phi, long ldphi,
+                                                      const cx<T>* __restrict__ buf,
+                                                      cx<T>* __restrict__ W, long ldW, int i0,
+                                                      int A, int j0, int nbc, int accumulate) {
+  constexpr int NN = N * N;
+  constexpr int LD = N + 1;
+  __shared__ cx<T> s[N * LD];
+  __shared__ cx<T> acc[ACC_LDS ? NN : 1];
+  const int x0 = blockIdx.x / nbc;
+  const int b = blockIdx.x - x0 * nbc;
+  const int t = threadIdx.x;
+  cx<T>* w = W + (size_t)(j0 + b) * ldW + (size_t)x0 * NN;
+  for (int a = 0; a < A; ++a) {
+    const size_t p = (size_t)a + (size_t)A * b;
+    const cx<T>* src = buf + p * N * NN + (size_t)x0 * NN;
+#pragma unroll 4
+    for (int r = 0; r < N; ++r) s[r * LD + t] = src[r * N + t];
+    __syncthreads();
+    cx<T> v[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
+    fft_line<N, +1, T>(v);
+#pragma unroll
+    for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = s[q * LD + t];
+    fft_line<N, +1, T>(v);
+    const cx<T>* f = phi + (size_t)(i0 + a) * ldphi + (size_t)x0 * NN;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int e = q * N + t;
+      const cx<T> prod = cmul(f[e], v[q]);
+      if (ACC_LDS) {
+        acc[e] = (a == 0) ? prod : cadd(acc[e], prod);
+      } else {
+        w[e] = (a == 0 && !accumulate) ? prod : cadd(w[e], prod);
+      }
+    }
+    __syncthreads();
+  }
+  if (ACC_LDS) {
+#pragma unroll 4
+    for (int q = 0; q < N; ++q) {
+      const int e = q * N + t;
+      w[e] = accumulate ? cadd(w[e], acc[e]) : acc[e];
+    }
+  }
+}
+
+// Energy pencil pass: forward FFT along axis 0 and sum_G K |rho^(G)|^2 for the
+// pencil; one partial per 64-pencil tile, weighted 2 for i < j (the j, i pair
+// has the same sum because K(G) = K(-G)).
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_pencil_energy(const cx<T>* __restrict__ buf,
+                                                      const T* __restrict__ Kt, long p0,
+                                                      double* __restrict__ partial) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  const int p = blockIdx.x / TILES;
+  const int q = (blockIdx.x - p * TILES) * 64 + threadIdx.x;
+  double sum = 0.0;
+  if (q < NN) {
+    const cx<T>* base = buf + (size_t)p * N * NN + q;
+    cx<T> v[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = base[(size_t)k * NN];
+    fft_line<N, -1, T>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double kk = (double)Kt[k * NN + q];
+      sum += kk * ((double)v[k].x * v[k].x + (double)v[k].y * v[k].y);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if (threadIdx.x == 0) {
+    int i, j;
+    pair_of(1, 0, 1, 0, p0, p, &i, &j);
+    partial[(size_t)(p0 + p) * TILES + (blockIdx.x - p * TILES)] = (i == j ? 1.0 : 2.0) * sum;
+  }
+}
+
+// Deterministic single-workgroup sum: *out = s * sum(x[0..n)).
+__global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ x, long n,
+                                                     double s, double* __restrict__ out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (long k = threadIdx.x; k < n; k += 1024) acc += x[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s * red[0];
+}
+
+size_t default_pair_budget() { return (size_t)1 << 30; }
+
+template <typename T>
+ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef) {
+  const unsigned blocks = (unsigned)((g.ng + 255) / 256);
+  return launch(c, "kernel_table", k_kernel_table<T>, dim3(blocks), dim3(256), 0, Kt, g.n, g.L[0],
+                g.L[1], g.L[2], g.kind, g.mu, g.g0, coef);
+}
+
+template <int N, typename T>
+ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
+                     const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  constexpr bool ACC_LDS = (size_t)(N * (N + 1) + NN) * sizeof(cx<T>) <= 150 * 1024;
+  const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
+  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
+  long maxpairs = (long)(budget / pair_bytes);
+  if (maxpairs < 1) maxpairs = 1;
+  const int A = (int)std::min<long>(nocc, maxpairs);
+  const int B = (int)std::max<long>(1, std::min<long>(nband, maxpairs / A));
+  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
+  ace_status st;
+  if ((st = ws_begin(c, kt_bytes + align_up((size_t)A * B * pair_bytes, 256))) != ACE_OK) return st;
+  T* Kt = (T*)ws_take(c, kt_bytes, &st);
+  cx<T>* buf = (cx<T>*)ws_take(c, (size_t)A * B * pair_bytes, &st);
+  if (!Kt || !buf) return st;
+  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng)) != ACE_OK) return st;
+  for (int j0 = 0; j0 < nband; j0 += B) {
+    const int Bc = std::min(B, nband - j0);
+    for (int i0 = 0; i0 < nocc; i0 += A) {
+      const int Ac = std::min(A, nocc - i0);
+      const int np = Ac * Bc;
+      if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(N * np), dim3(N), 0, phi,
+                       ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) != ACE_OK)
+        return st;
+      if ((st = launch(c, "pencil_kernel", k_pencil_kernel<N, T>, dim3(np * TILES), dim3(64), 0,
+                       buf, (const T*)Kt)) != ACE_OK)
+        return st;
+      if ((st = launch(c, "inv_slab_accum", k_inv_slab_accum<N, T, ACC_LDS>, dim3(N * Bc),
+                       dim3(N), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
+                       i0 > 0 ? 1 : 0)) != ACE_OK)
+        return st;
+    }
+  }
+  return ACE_OK;
+}
+
+template <int N, typename T>
+ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
+                           double* ex_dev) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  const long total = (long)nocc * (nocc + 1) / 2;
+  const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
+  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
+  long chunk = std::max<long>(1, (long)(budget / pair_bytes));
+  chunk = std::min(chunk, total);
+  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
+  const size_t part_bytes = align_up((size_t)total * TILES * sizeof(double), 256);
+  ace_status st;
+  if ((st = ws_begin(c, kt_bytes + part_bytes + align_up((size_t)chunk * pair_bytes, 256))) !=
+      ACE_OK)
+    return st;
+  T* Kt = (T*)ws_take(c, kt_bytes, &st);
+  double* partial = (double*)ws_take(c, part_bytes, &st);
+  cx<T>* buf = (cx<T>*)ws_take(c, (size_t)chunk * pair_bytes, &st);
+  if (!Kt || !partial || !buf) return st;
+  if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
+  for (long p0 = 0; p0 < total; p0 += chunk) {
+    const int np = (int)std::min(chunk, total - p0);
+    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(N * np), dim3(N), 0, phi,
+                     ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0, np)) != ACE_OK)
+      return st;
+    if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(64), 0,
+                     (const cx<T>*)buf, (const T*)Kt, p0, partial)) != ACE_OK)
+      return st;
+  }
+  return launch(c, "sum_scaled", k_sum_scaled, dim3(1), dim3(1024), 0, (const double*)partial,
+                total * TILES, -0.5 * g.dV / (double)g.ng, ex_dev);
+}
+
+}  // namespace
+
+template <typename T>
+ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
+                        const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW,
+                        double scale) {
+  switch (g.n) {
+#define ACE_CASE(NV) \
+  case NV:           \
+    return build_W_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale);
+    ACE_FOR_EACH_N(ACE_CASE)
+#undef ACE_CASE
+    default:
+      return fail(c, ACE_E_UNSUPPORTED, "grid size not compiled into the library");
+  }
+}
+
+template <typename T>
+ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
+                              long ldphi, double* ex_dev) {
+  switch (g.n) {
+#define ACE_CASE(NV) \
+  case NV:           \
+    return energy_direct_n<NV, T>(c, g, phi, nocc, ldphi, ex_dev);
+    ACE_FOR_EACH_N(ACE_CASE)
+#undef ACE_CASE
+    default:
+      return fail(c, ACE_E_UNSUPPORTED, "grid size not compiled into the library");
+  }
+}
+
+template ace_status build_W_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int, long,
+                                        const cx<float>*, int, long, cx<float>*, long, double);
+template ace_status build_W_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int, long,
+                                         const cx<double>*, int, long, cx<double>*, long, double);
+template ace_status energy_direct_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int,
+                                              long, double*);
+template ace_status energy_direct_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int,
+                                               long, double*);
+
+}  // namespace ace
