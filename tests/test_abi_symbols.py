@@ -17,7 +17,7 @@ def _declared():
         if fn.endswith(".h"):
             text = open(os.path.join(ROOT, "include", fn)).read()
             text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-            names |= set(re.findall(r"\b(ace_[a-z0-9_]+)\s*\(", text))
+            names |= set(re.findall(r"\b(ace_[A-Za-z0-9_]+)\s*\(", text))
     return names
 
 
