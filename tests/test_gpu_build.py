@@ -90,8 +90,10 @@ def test_build_W_rejects_bad_arguments(ace):
     import torch
     n = 16
     x = torch.zeros((2, n ** 3), dtype=torch.complex128, device="cuda")
+    y = torch.zeros((2, 17 ** 3), dtype=torch.complex128, device="cuda")
+    z = torch.zeros_like(y)
     with pytest.raises(ace.AceError) as e:
-        ace.build_W(x, x, ace.Grid.cubic(17, 5.0), "fp64")     # unsupported n
+        ace.build_W(y, y, ace.Grid.cubic(17, 5.0), "fp64", out=z)   # unsupported n
     assert e.value.status == 5
     with pytest.raises(ace.AceError) as e:
         ace.build_W(x, x, ace.Grid.cubic(16, -1.0), "fp64")    # bad cell
