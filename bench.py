@@ -166,16 +166,16 @@ def main():
     log(f"bench: {ms_step:.3f} ms/step, stages {st_ms}")
 
     # dominant FFT-pass kernel and its roofline
-    fft_kernels = {"pair_fwd_slab": 3, "pencil_kernel": 2, "inv_slab_accum": 1}
-    dom = max(fft_kernels, key=lambda k: prof.get(k, {"ms": 0})["ms"])
+    # algorithmic HBM bytes per pair, in units of N_g * s:
+    #   pair_fwd_slab: write the slab spectra (inputs amortised over the pair block)
+    #   plane_kernel:  read + write
+    #   pencil_accum:  read (phi and W amortised over the pair block)
+    fft_units = {"pair_fwd_slab": 1, "plane_kernel": 2, "pencil_accum": 1}
+    dom = max(fft_units, key=lambda k: prof.get(k, {"ms": 0})["ms"])
     d = prof[dom]
     avg_ms = d["ms"] / d["launches"]
     pairs_per_launch = pairs * args.steps / d["launches"]
-    # algorithmic HBM bytes per pair for each pass:
-    #   forward slab: write N_g s (inputs amortised over the pair block, not counted)
-    #   pencil: read + write N_g s
-    #   inverse slab: read N_g s (phi and W amortised over the block, not counted)
-    bytes_per_pair = {"pair_fwd_slab": 1, "pencil_kernel": 2, "inv_slab_accum": 1}[dom] * ng * sbytes
+    bytes_per_pair = fft_units[dom] * ng * sbytes
     achieved = bytes_per_pair * pairs_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -168,6 +168,14 @@ ace_status ace_profile_get(ace_ctx ctx, int idx, const char** name, long* launch
  * (the FFT intermediates of a block of pairs).  0 restores the default. */
 ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
 
+/* Tuning knobs of the build (values >= 0; 0 = automatic choice):
+ *  ACE_TUNE_PAIR_BUDGET  same as ace_set_pair_budget (bytes)
+ *  ACE_TUNE_JBLOCK       bands j per pair block of the build
+ * They change speed only; results agree to rounding. */
+enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1 };
+ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
+ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
+
 const char* ace_status_string(ace_status s);
 const char* ace_last_error(ace_ctx ctx);
 

@@ -15,8 +15,10 @@ EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
     "ace_apply", "ace_exchange_energy", "ace_orthonormalize", "ace_supported_n",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
-    "ace_set_pair_budget", "ace_status_string", "ace_last_error",
+    "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
+    "ace_last_error",
 ]
+ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK = 0, 1
 
 
 class AceGrid(ctypes.Structure):
@@ -47,6 +49,8 @@ _PROTOS = {
     "ace_profile_get": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_l),
                              ctypes.POINTER(_d)]),
     "ace_set_pair_budget": (_i, [_vp, _l]),
+    "ace_set_tuning": (_i, [_vp, _i, _l]),
+    "ace_get_tuning": (_i, [_vp, _i, ctypes.POINTER(_l)]),
     "ace_status_string": (ctypes.c_char_p, [_i]),
     "ace_last_error": (ctypes.c_char_p, [_vp]),
 }

@@ -148,6 +148,16 @@ class Context:
     def set_pair_budget(self, nbytes: int):
         self._check(self._lib.ace_set_pair_budget(self._h, int(nbytes)))
 
+    def set_tuning(self, key: str, value: int):
+        k = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK}[key]
+        self._check(self._lib.ace_set_tuning(self._h, k, int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        k = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK}[key]
+        v = ctypes.c_long()
+        self._check(self._lib.ace_get_tuning(self._h, k, ctypes.byref(v)))
+        return v.value
+
     def build_W(self, phi, psi, grid: Grid, prec, scale: float = 1.0, out=None):
         """W = scale * V_X[phi] psi (pair Poisson solves)."""
         p = _prec(prec)

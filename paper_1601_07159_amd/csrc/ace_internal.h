@@ -18,6 +18,8 @@ struct ace_ctx_s {
   size_t ws_bytes = 0;
   size_t ws_used = 0;
   size_t pair_budget = 0;  // 0 = default
+  long jblock = 0;         // band block of the build; 0 = automatic
+  int num_cus = 256;
   std::string last_error;
   // profiling
   bool profiling = false;

@@ -303,6 +303,11 @@ ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream) {
     delete c;
     return ACE_E_HIP;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) ==
+          hipSuccess &&
+      cus > 0)
+    c->num_cus = cus;
   *out = c;
   return ACE_OK;
 }
@@ -334,6 +339,24 @@ ACE_EXPORT ace_status ace_set_pair_budget(ace_ctx c, long bytes) {
   return ACE_OK;
 }
 
+ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
+  if (!c || value < 0) return ACE_E_ARG;
+  switch (key) {
+    case ACE_TUNE_PAIR_BUDGET: c->pair_budget = (size_t)value; return ACE_OK;
+    case ACE_TUNE_JBLOCK: c->jblock = value; return ACE_OK;
+    default: return fail(c, ACE_E_ARG, "unknown tuning key");
+  }
+}
+
+ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
+  if (!c || !value) return ACE_E_ARG;
+  switch (key) {
+    case ACE_TUNE_PAIR_BUDGET: *value = (long)c->pair_budget; return ACE_OK;
+    case ACE_TUNE_JBLOCK: *value = c->jblock; return ACE_OK;
+    default: return fail(c, ACE_E_ARG, "unknown tuning key");
+  }
+}
+
 ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec, int max_nocc,
                                   int max_nband, int max_nx) {
   if (!c) return ACE_E_ARG;
@@ -342,7 +365,7 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   if (max_nocc < 1 || max_nband < 1 || max_nx < 0) return fail(c, ACE_E_ARG, "sizes");
   const size_t eb = elem_bytes(prec);
   const size_t pair_bytes = (size_t)g.ng * eb;
-  const size_t budget = c->pair_budget ? c->pair_budget : ((size_t)1 << 30);
+  const size_t budget = c->pair_budget ? c->pair_budget : ((size_t)2 << 30);
   size_t pairs = std::max<size_t>(1, budget / pair_bytes);
   pairs = std::min<size_t>(pairs, (size_t)max_nocc * max_nband);
   size_t need = align_up(pairs * pair_bytes, 256) + align_up((size_t)g.ng * 8, 256) +

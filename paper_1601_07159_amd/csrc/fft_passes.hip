@@ -7,14 +7,15 @@
 //   slab pass (forward)   one workgroup per (x0 slab, pair): the pair product is
 //                         formed while the slab is loaded, then 2-D FFT over
 //                         axes 2 and 1 in LDS; spectrum slab written out.
-//   pencil pass           one thread per (k1, k2) pencil along axis 0: forward
-//                         FFT, multiply by the scaled kernel, inverse FFT, all
-//                         in registers; lanes of a wave read consecutive
-//                         pencils, so every load is a contiguous 64-lane row.
-//   slab pass (inverse)   one workgroup per (x0 slab, band j): loops over the
-//                         occupied orbitals i of the block, inverse 2-D FFT of
-//                         u_ij, multiply by phi_i and accumulate into w_j,
-//                         which is written once per block (no atomics).
+//   plane pass            one workgroup per (k1 plane, pair): along axis 0 the
+//                         forward FFT, the multiply by the scaled kernel and
+//                         the inverse FFT, then the inverse FFT along axis 2,
+//                         all through LDS.
+//   pencil pass           one thread per (x0, x2) pencil along axis 1, lanes
+//                         on consecutive pencils: loops over the occupied
+//                         orbitals i of the block, inverse FFT, multiply by
+//                         phi_i, accumulate in thread-private LDS; w_j is
+//                         written once per block (no atomics, no barriers).
 // The 1/N_g of the inverse transform, the minus sign and the caller's scale are
 // folded into the kernel table K'(G) = -scale K(G) / N_g.
 #include <cmath>
@@ -54,6 +55,18 @@ __global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n,
   Kt[idx] = T(coef * K);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
+// physical workgroup b runs on XCD b % 8.  The launches pad the grid to a
+// multiple of 8 and map physical ids so that XCD x receives the contiguous
+// logical range [x G/8, (x+1) G/8); logical ids >= count exit at once.  Logical
+// order is chosen so that neighbours share inputs (the same x0 slab of phi and
+// psi, the same pencil tile of phi), which then stay in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long xcd_logical(long bid, long padded) {
+  return (bid % kXcds) * (padded / kXcds) + bid / kXcds;
+}
+inline unsigned xcd_pad(long count) { return (unsigned)((count + kXcds - 1) / kXcds * kXcds); }
+
 // Pair of block-local index p.
 //  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
 //  mode 1: upper triangle i <= j, global triangle index p0 + p (row-major in j)
@@ -81,15 +94,25 @@ __global__ __launch_bounds__(N) void k_pair_fwd_slab(const cx<T>* __restrict__ p
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
   __shared__ cx<T> s[N * LD];
-  const int x0 = blockIdx.x / npairs;
-  const int p = blockIdx.x - x0 * npairs;
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int x0 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)x0 * npairs);
   int i, j;
   pair_of(mode, i0, A, j0, p0, p, &i, &j);
   const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
   const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
   const int t = threadIdx.x;
-#pragma unroll 4
-  for (int r = 0; r < N; ++r) s[r * LD + t] = cmulc(a[r * N + t], b[r * N + t]);
+  {
+    // issue every load of the slab before the first use
+    cx<T> va[N], vb[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) va[r] = a[r * N + t];
+#pragma unroll
+    for (int r = 0; r < N; ++r) vb[r] = b[r * N + t];
+#pragma unroll
+    for (int r = 0; r < N; ++r) s[r * LD + t] = cmulc(va[r], vb[r]);
+  }
   __syncthreads();
   cx<T> v[N];
 #pragma unroll
@@ -106,80 +129,100 @@ __global__ __launch_bounds__(N) void k_pair_fwd_slab(const cx<T>* __restrict__ p
   for (int q = 0; q < N; ++q) out[q * N + t] = v[q];
 }
 
-// Pencil pass: forward FFT along axis 0, multiply by K', inverse FFT.
+// Plane pass: one workgroup of N threads per (k1 plane, pair).  The plane
+// buf[k0][k1][.] (N rows of N contiguous values, rows N^2 apart) goes through
+// LDS: forward FFT along axis 0, multiply by K', inverse FFT along axis 0, then
+// inverse FFT along axis 2.  Loads and stores are contiguous N-wide rows.
 template <int N, typename T>
-__global__ __launch_bounds__(64) void k_pencil_kernel(cx<T>* __restrict__ buf,
-                                                      const T* __restrict__ Kt) {
-  constexpr int NN = N * N;
-  constexpr int TILES = (NN + 63) / 64;
-  const int p = blockIdx.x / TILES;
-  const int q = (blockIdx.x - p * TILES) * 64 + threadIdx.x;
-  if (q >= NN) return;
-  cx<T>* base = buf + (size_t)p * N * NN + q;
-  cx<T> v[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = base[(size_t)k * NN];
-  fft_line<N, -1, T>(v);
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const T kk = Kt[k * NN + q];
-    v[k].x *= kk;
-    v[k].y *= kk;
-  }
-  fft_line<N, +1, T>(v);
-#pragma unroll
-  for (int k = 0; k < N; ++k) base[(size_t)k * NN] = v[k];
-}
-
-// Inverse slab pass with the phi-multiply and accumulation over the i block.
-template <int N, typename T, bool ACC_LDS>
-__global__ __launch_bounds__(N) void k_inv_slab_accum(const cx<T>* __restrict__ phi, long ldphi,
-                                                      const cx<T>* __restrict__ buf,
-                                                      cx<T>* __restrict__ W, long ldW, int i0,
-                                                      int A, int j0, int nbc, int accumulate) {
+__global__ __launch_bounds__(N) void k_plane_kernel(cx<T>* __restrict__ buf,
+                                                    const T* __restrict__ Kt, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
   __shared__ cx<T> s[N * LD];
-  __shared__ cx<T> acc[ACC_LDS ? NN : 1];
-  const int x0 = blockIdx.x / nbc;
-  const int b = blockIdx.x - x0 * nbc;
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int k1 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)k1 * npairs);
   const int t = threadIdx.x;
-  cx<T>* w = W + (size_t)(j0 + b) * ldW + (size_t)x0 * NN;
-  for (int a = 0; a < A; ++a) {
-    const size_t p = (size_t)a + (size_t)A * b;
-    const cx<T>* src = buf + p * N * NN + (size_t)x0 * NN;
-#pragma unroll 4
-    for (int r = 0; r < N; ++r) s[r * LD + t] = src[r * N + t];
-    __syncthreads();
-    cx<T> v[N];
+  cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
+  cx<T> v[N];
+  // axis 0 (column t of the plane, k2 = t): forward, kernel, inverse.  The
+  // column is read straight from global memory (lanes on consecutive k2).
 #pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
-    fft_line<N, +1, T>(v);
+  for (int r = 0; r < N; ++r) v[r] = plane[(size_t)r * NN + t];
+  fft_line<N, -1, T>(v);
+  const T* kcol = Kt + (size_t)k1 * N + t;
 #pragma unroll
-    for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = s[q * LD + t];
-    fft_line<N, +1, T>(v);
-    const cx<T>* f = phi + (size_t)(i0 + a) * ldphi + (size_t)x0 * NN;
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      const int e = q * N + t;
-      const cx<T> prod = cmul(f[e], v[q]);
-      if (ACC_LDS) {
-        acc[e] = (a == 0) ? prod : cadd(acc[e], prod);
-      } else {
-        w[e] = (a == 0 && !accumulate) ? prod : cadd(w[e], prod);
-      }
-    }
-    __syncthreads();
+  for (int r = 0; r < N; ++r) {
+    const T kk = kcol[(size_t)r * NN];
+    v[r].x *= kk;
+    v[r].y *= kk;
   }
-  if (ACC_LDS) {
-#pragma unroll 4
-    for (int q = 0; q < N; ++q) {
-      const int e = q * N + t;
-      w[e] = accumulate ? cadd(w[e], acc[e]) : acc[e];
-    }
+  fft_line<N, +1, T>(v);
+#pragma unroll
+  for (int r = 0; r < N; ++r) s[r * LD + t] = v[r];
+  __syncthreads();
+  // axis 2 (row t of the plane, x0 = t): inverse
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
+  fft_line<N, +1, T>(v);
+#pragma unroll
+  for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < N; ++r) plane[(size_t)r * NN + t] = s[r * LD + t];
+}
+
+// Pencil pass with accumulation: one thread per (x0, x2) pencil along axis 1,
+// 64 pencils per workgroup, one band j per workgroup row of the grid.  Loops
+// over the occupied orbitals i of the block: inverse FFT along axis 1, multiply
+// by phi_i, accumulate into a thread-private LDS column; w_j is written once
+// per block.  Lanes hold consecutive pencils, so every global access is a
+// contiguous row; no barrier is needed anywhere.
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ phi, long ldphi,
+                                                     const cx<T>* __restrict__ buf,
+                                                     cx<T>* __restrict__ W, long ldW, int i0,
+                                                     int A, int j0, int nbc, int accumulate) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  __shared__ cx<T> acc[N * 64];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)TILES * nbc) return;
+  const int tile = (int)(lid / nbc);
+  const int b = (int)(lid - (long)tile * nbc);
+  const int t = threadIdx.x;
+  const int q = tile * 64 + t;
+  if (q >= NN) return;
+  const int x0 = q / N, x2 = q - x0 * N;
+  const size_t off = (size_t)x0 * NN + x2;
+  // Branch-free body: the accumulator starts at zero, and all loads of an
+  // iteration (the pencil of u_ij and of phi_i) are issued before any use.
+#pragma unroll
+  for (int k = 0; k < N; ++k) acc[k * 64 + t] = cx<T>{T(0), T(0)};
+  for (int a = 0; a < A; ++a) {
+    const cx<T>* src = buf + ((size_t)a + (size_t)A * b) * N * NN + off;
+    const cx<T>* fp = phi + (size_t)(i0 + a) * ldphi + off;
+    cx<T> v[N];
+    cx<T> f[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = src[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) f[k] = fp[k * N];
+    fft_line<N, +1, T>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k * 64 + t] = cadd(acc[k * 64 + t], cmul(f[k], v[k]));
+  }
+  cx<T>* w = W + (size_t)(j0 + b) * ldW + off;
+  if (accumulate) {
+    cx<T> old[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) old[k] = w[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k * N] = cadd(old[k], acc[k * 64 + t]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k * N] = acc[k * 64 + t];
   }
 }
 
@@ -230,7 +273,7 @@ __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ 
   if (threadIdx.x == 0) *out = s * red[0];
 }
 
-size_t default_pair_budget() { return (size_t)1 << 30; }
+size_t default_pair_budget() { return (size_t)2 << 30; }
 
 template <typename T>
 ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef) {
@@ -244,13 +287,16 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
                      const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
-  constexpr bool ACC_LDS = (size_t)(N * (N + 1) + NN) * sizeof(cx<T>) <= 150 * 1024;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
   const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
   long maxpairs = (long)(budget / pair_bytes);
   if (maxpairs < 1) maxpairs = 1;
-  const int A = (int)std::min<long>(nocc, maxpairs);
-  const int B = (int)std::max<long>(1, std::min<long>(nband, maxpairs / A));
+  // Band block B (all bands unless the tuning knob says otherwise): the
+  // accumulating pass runs TILES * B one-wave workgroups, each looping over the
+  // i block, and W is read-modified-written once per i block.
+  int B = c->jblock > 0 ? (int)std::min<long>(nband, c->jblock) : nband;
+  B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
+  const int A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
   const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
   if ((st = ws_begin(c, kt_bytes + align_up((size_t)A * B * pair_bytes, 256))) != ACE_OK) return st;
@@ -263,14 +309,14 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
     for (int i0 = 0; i0 < nocc; i0 += A) {
       const int Ac = std::min(A, nocc - i0);
       const int np = Ac * Bc;
-      if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(N * np), dim3(N), 0, phi,
-                       ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) != ACE_OK)
+      if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * np)),
+                       dim3(N), 0, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) != ACE_OK)
         return st;
-      if ((st = launch(c, "pencil_kernel", k_pencil_kernel<N, T>, dim3(np * TILES), dim3(64), 0,
-                       buf, (const T*)Kt)) != ACE_OK)
+      if ((st = launch(c, "plane_kernel", k_plane_kernel<N, T>, dim3(xcd_pad((long)N * np)),
+                       dim3(N), 0, buf, (const T*)Kt, np)) != ACE_OK)
         return st;
-      if ((st = launch(c, "inv_slab_accum", k_inv_slab_accum<N, T, ACC_LDS>, dim3(N * Bc),
-                       dim3(N), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
+      if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * Bc)),
+                       dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
                        i0 > 0 ? 1 : 0)) != ACE_OK)
         return st;
     }
@@ -301,8 +347,8 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
   for (long p0 = 0; p0 < total; p0 += chunk) {
     const int np = (int)std::min(chunk, total - p0);
-    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(N * np), dim3(N), 0, phi,
-                     ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0, np)) != ACE_OK)
+    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * np)),
+                     dim3(N), 0, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0, np)) != ACE_OK)
       return st;
     if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(64), 0,
                      (const cx<T>*)buf, (const T*)Kt, p0, partial)) != ACE_OK)
