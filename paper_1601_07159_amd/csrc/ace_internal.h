@@ -102,16 +102,13 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
 template <typename T>
 ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
                    int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate);
-// In place: A (n x n, lower part) -> L with A = L L^H; info_dev gets 0 or the
-// failing pivot.  A nonzero *prior (nullable) is propagated instead.
-ace_status cholesky(ace_ctx c, cx<double>* A, int n, int* info_dev, const int* prior = nullptr);
-// Hermitian part of a square matrix scaled: A <- s * (A + A^H)/2
-ace_status hermitize(ace_ctx c, cx<double>* A, int n, double s);
-// Given L (lower), writes C = L^{-H} (upper) into C.
-ace_status tri_inv_herm(ace_ctx c, const cx<double>* L, int n, cx<double>* C, cx<double>* scratch,
-                        const int* info_dev);
+// Fused: A = s (M + M^H)/2, A = L L^H, Lout = L (nullable), C = L^{-H}.
+// scratch: n x n complex128 (used when n is too large for LDS).  info_dev gets
+// 0 or the first failing pivot; a nonzero *prior (nullable) is propagated.
+ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
+                    cx<double>* C, cx<double>* scratch, int* info_dev,
+                    const int* prior = nullptr);
 // *out = s * sum |A_ij|^2 over an m x n column-major block
 ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out);
-ace_status copy_matrix(ace_ctx c, const cx<double>* src, int n, cx<double>* dst);
 
 }  // namespace ace

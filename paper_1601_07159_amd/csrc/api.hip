@@ -201,10 +201,8 @@ static ace_status compress_t(ace_ctx c, const GridInfo& g, const cx<T>* psi, lon
   if (!M || !X || !C || !info) return st;
   // M = dV psi^H W, then -M made exactly Hermitian
   ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed));
-  ACE_TRY(hermitize(c, M, nb, -1.0));
-  ACE_TRY(cholesky(c, M, nb, info));
-  if (L_out) ACE_TRY(copy_matrix(c, M, nb, L_out));
-  ACE_TRY(tri_inv_herm(c, M, nb, C, X, info));
+  // -M made exactly Hermitian, -M = L L^H, C = L^{-H}
+  ACE_TRY(chol_inv(c, M, nb, -1.0, L_out, C, X, info));
   ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true));
   return finish_info(c, info, info_dev);
 }
@@ -249,15 +247,11 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
   // round 1: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
   ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false));
-  ACE_TRY(hermitize(c, S, n, 1.0));
-  ACE_TRY(cholesky(c, S, n, info1));
-  ACE_TRY(tri_inv_herm(c, S, n, C, Xs, info1));
+  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1));
   ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true));
   // round 2 on Y restores orthogonality lost to rounding in round 1
   ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false));
-  ACE_TRY(hermitize(c, S, n, 1.0));
-  ACE_TRY(cholesky(c, S, n, info2, info1));
-  ACE_TRY(tri_inv_herm(c, S, n, C, Xs, info2));
+  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1));
   ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true));
   return finish_info(c, info2, info_dev);
 }
