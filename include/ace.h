@@ -142,6 +142,20 @@ ace_status ace_exchange_energy(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                                double* ex_dev);
 
 /*
+ * Orbital gradient of E_X(phi) = 1/2 sum_i <phi_i, V_X[phi] phi_i>  (Eq. EX),
+ * written in the convention PyTorch uses for complex leaves (twice the
+ * conjugate Wirtinger derivative), scaled by an upstream gradient:
+ *   G_i = 2 gbar dE_X/dphi_i^* = 2 gbar dV (V_X[phi] phi)_i,
+ * because each of the two conj(phi) factors of the quartic E_X contributes one
+ * half.  gbar_dev: one device double (nullable: 1).  The pair FFTs are
+ * recomputed, none is stored between forward and backward.  G: n_occ orbitals,
+ * must not overlap phi.
+ */
+ace_status ace_exchange_energy_grad(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                                    const void* phi, int n_occ, long ld_phi,
+                                    const double* gbar_dev, void* G, long ld_G);
+
+/*
  * Orthonormalise n vectors: Q = X R^{-1} with <Q_a, Q_b> = delta_ab and R upper
  * triangular with positive real diagonal (the constraint of Eq. HF).  Computed
  * as two rounds of Cholesky QR in FP64 (Gram matrix, Cholesky, triangular
@@ -168,11 +182,14 @@ ace_status ace_profile_get(ace_ctx ctx, int idx, const char** name, long* launch
  * (the FFT intermediates of a block of pairs).  0 restores the default. */
 ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
 
-/* Tuning knobs of the build (values >= 0; 0 = automatic choice):
- *  ACE_TUNE_PAIR_BUDGET  same as ace_set_pair_budget (bytes)
- *  ACE_TUNE_JBLOCK       bands j per pair block of the build
+/* Tuning knobs of the build (values >= 0):
+ *  ACE_TUNE_PAIR_BUDGET  same as ace_set_pair_budget (bytes; 0 = default)
+ *  ACE_TUNE_JBLOCK       bands j per pair block of the build (0 = all)
+ *  ACE_TUNE_SYMMETRY     1 (default): when psi's first n_occ orbitals are phi
+ *                        (same pointer and ld), FFT only the pairs i <= j of the
+ *                        occupied block and use u_ji = conj(u_ij); 0: all pairs
  * They change speed only; results agree to rounding. */
-enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1 };
+enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2 };
 ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
 ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
 

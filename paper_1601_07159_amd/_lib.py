@@ -13,12 +13,13 @@ ACE_COULOMB, ACE_ERFC = 0, 1
 
 EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
-    "ace_apply", "ace_exchange_energy", "ace_orthonormalize", "ace_supported_n",
+    "ace_apply", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
+    "ace_supported_n",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
     "ace_last_error",
 ]
-ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK = 0, 1
+ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY = 0, 1, 2
 
 
 class AceGrid(ctypes.Structure):
@@ -41,6 +42,7 @@ _PROTOS = {
     "ace_compress": (_i, [_vp, _gp, _i, _vp, _l, _vp, _l, _i, _vp, _l, _vp, _vp]),
     "ace_apply": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l]),
     "ace_exchange_energy": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp]),
+    "ace_exchange_energy_grad": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _vp, _l]),
     "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
     "ace_profile_enable": (_i, [_vp, _i]),

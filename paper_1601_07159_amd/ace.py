@@ -20,6 +20,8 @@ from . import _lib
 from ._lib import ACE_FP32, ACE_FP64, ACE_MIXED  # noqa: F401
 
 PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED}
+_TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
+              "symmetry": _lib.ACE_TUNE_SYMMETRY}
 
 
 class AceError(RuntimeError):
@@ -149,13 +151,11 @@ class Context:
         self._check(self._lib.ace_set_pair_budget(self._h, int(nbytes)))
 
     def set_tuning(self, key: str, value: int):
-        k = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK}[key]
-        self._check(self._lib.ace_set_tuning(self._h, k, int(value)))
+        self._check(self._lib.ace_set_tuning(self._h, _TUNE_KEYS[key], int(value)))
 
     def get_tuning(self, key: str) -> int:
-        k = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK}[key]
         v = ctypes.c_long()
-        self._check(self._lib.ace_get_tuning(self._h, k, ctypes.byref(v)))
+        self._check(self._lib.ace_get_tuning(self._h, _TUNE_KEYS[key], ctypes.byref(v)))
         return v.value
 
     def build_W(self, phi, psi, grid: Grid, prec, scale: float = 1.0, out=None):
@@ -230,6 +230,24 @@ class Context:
                                                   ldb, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def exchange_energy_grad(self, phi, grid: Grid, prec, gbar=None, out=None):
+        """G = 2 gbar dV V_X[phi] phi (PyTorch's gradient of E_X for complex phi)."""
+        p = _prec(prec)
+        a, na, lda = _block(phi, p, grid.ng, "phi")
+        if out is None:
+            out = torch.empty_like(phi, memory_format=torch.contiguous_format)
+        o, no, ldo = _block(out, p, grid.ng, "G")
+        gp = None
+        if gbar is not None:
+            if gbar.dtype != torch.float64 or not gbar.is_cuda or gbar.numel() != 1:
+                raise TypeError("gbar must be a one-element CUDA float64 tensor")
+            gp = ctypes.c_void_p(gbar.data_ptr())
+        g = grid.as_c()
+        self._bind_stream()
+        self._check(self._lib.ace_exchange_energy_grad(self._h, ctypes.byref(g), p, a, na, lda,
+                                                       gp, o, ldo))
+        return out
+
     def orthonormalize(self, X, grid: Grid, prec, info=None, out=None):
         p = _prec(prec)
         a, na, lda = _block(X, p, grid.ng, "X")
@@ -297,3 +315,32 @@ def exchange_energy(phi, grid, prec, xi=None, out=None):
 
 def orthonormalize(X, grid, prec, info=None, out=None):
     return context(X.device).orthonormalize(X, grid, prec, info, out)
+
+
+def exchange_energy_grad(phi, grid, prec, gbar=None, out=None):
+    return context(phi.device).exchange_energy_grad(phi, grid, prec, gbar, out)
+
+
+class ExchangeEnergy(torch.autograd.Function):
+    """E_X(phi) = 1/2 sum_i <phi_i, V_X[phi] phi_i> with a hand-written backward.
+
+    forward: Parseval sum over the pair spectra i <= j (forward FFTs only);
+    backward: the orbital gradient 2 gbar dV V_X[phi] phi, recomputing the
+    pair FFTs instead of storing them.  Usage: ExchangeEnergy.apply(phi, grid, prec).
+    """
+
+    @staticmethod
+    def forward(ctx, phi, grid, prec):
+        phi = phi.contiguous()
+        e = exchange_energy(phi, grid, prec)
+        ctx.save_for_backward(phi)
+        ctx.grid = grid
+        ctx.prec = prec
+        return e
+
+    @staticmethod
+    def backward(ctx, gbar):
+        (phi,) = ctx.saved_tensors
+        gb = gbar.detach().to(torch.float64).reshape(1).contiguous()
+        g = exchange_energy_grad(phi, ctx.grid, ctx.prec, gbar=gb)
+        return g, None, None

@@ -19,6 +19,7 @@ struct ace_ctx_s {
   size_t ws_used = 0;
   size_t pair_budget = 0;  // 0 = default
   long jblock = 0;         // band block of the build; 0 = automatic
+  bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
   int num_cus = 256;
   std::string last_error;
   // profiling
@@ -86,9 +87,11 @@ struct GridInfo {
 };
 
 // Pair FFT stages (fft_passes.hip).
+// W = scale * (*dscale if dscale else 1) * V_X[phi] psi
 template <typename T>
 ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
-                        const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale);
+                        const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale,
+                        const double* dscale = nullptr);
 template <typename T>
 ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
                               long ldphi, double* ex_dev);

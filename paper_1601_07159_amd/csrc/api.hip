@@ -338,6 +338,7 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
   switch (key) {
     case ACE_TUNE_PAIR_BUDGET: c->pair_budget = (size_t)value; return ACE_OK;
     case ACE_TUNE_JBLOCK: c->jblock = value; return ACE_OK;
+    case ACE_TUNE_SYMMETRY: c->use_symmetry = value != 0; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }
@@ -347,6 +348,7 @@ ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
   switch (key) {
     case ACE_TUNE_PAIR_BUDGET: *value = (long)c->pair_budget; return ACE_OK;
     case ACE_TUNE_JBLOCK: *value = c->jblock; return ACE_OK;
+    case ACE_TUNE_SYMMETRY: *value = c->use_symmetry ? 1 : 0; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }
@@ -457,6 +459,27 @@ ACE_EXPORT ace_status ace_exchange_energy(ace_ctx c, const ace_grid* grid, ace_p
   if (prec == ACE_FP64)
     return energy_direct_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi, ex_dev);
   return energy_direct_impl<float>(c, g, (const cx<float>*)phi, n_occ, ld_phi, ex_dev);
+}
+
+ACE_EXPORT ace_status ace_exchange_energy_grad(ace_ctx c, const ace_grid* grid, ace_prec prec,
+                                               const void* phi, int n_occ, long ld_phi,
+                                               const double* gbar_dev, void* G, long ld_G) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  ACE_TRY(check_block(c, phi, n_occ, ld_phi, g, "phi"));
+  ACE_TRY(check_block(c, G, n_occ, ld_G, g, "G"));
+  const size_t eb = elem_bytes(prec);
+  if (overlap(span_of(G, n_occ, ld_G, g.ng, eb), span_of(phi, n_occ, ld_phi, g.ng, eb)))
+    return fail(c, ACE_E_ARG, "G overlaps phi");
+  // G = 2 gbar dV V_X[phi] phi: the pair FFTs are recomputed (pairs i <= j)
+  const double scale = 2.0 * g.dV;
+  if (prec == ACE_FP64)
+    return build_W_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi,
+                                (const cx<double>*)phi, n_occ, ld_phi, (cx<double>*)G, ld_G, scale,
+                                gbar_dev);
+  return build_W_impl<float>(c, g, (const cx<float>*)phi, n_occ, ld_phi, (const cx<float>*)phi,
+                             n_occ, ld_phi, (cx<float>*)G, ld_G, scale, gbar_dev);
 }
 
 ACE_EXPORT ace_status ace_orthonormalize(ace_ctx c, const ace_grid* grid, ace_prec prec,

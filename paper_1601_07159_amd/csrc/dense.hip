@@ -24,23 +24,26 @@ namespace {
 constexpr int kCholLdsMax = 88;
 
 __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, int n, double s,
-                              cx<double>* A, int lda, cx<double>* __restrict__ Lout,
-                              cx<double>* __restrict__ C, int* __restrict__ info,
-                              const int* __restrict__ prior) {
+                                              cx<double>* A, int lda,
+                                              cx<double>* __restrict__ Lout,
+                                              cx<double>* __restrict__ C, int* __restrict__ info,
+                                              const int* __restrict__ prior) {
+  // Element loops: waves stride over columns, lanes over rows (consecutive
+  // rows are consecutive in memory), so no integer division is needed.
   __shared__ int failed;
   const int t = threadIdx.x, nt = blockDim.x;
+  const int lane = t & 63, wave = t >> 6, nw = nt >> 6;
   if (prior && *prior != 0) {
     if (t == 0) *info = *prior;
     return;
   }
   if (t == 0) failed = 0;
-  for (long e = t; e < (long)n * n; e += nt) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    if (i < j) continue;
-    const cx<double> a = M[i + (size_t)j * n], b = M[j + (size_t)i * n];
-    A[i + (size_t)j * lda] = (i == j) ? cx<double>{s * a.x, 0.0}
-                                      : cx<double>{0.5 * s * (a.x + b.x), 0.5 * s * (a.y - b.y)};
-  }
+  for (int j = wave; j < n; j += nw)
+    for (int i = j + lane; i < n; i += 64) {
+      const cx<double> a = M[i + (size_t)j * n], b = M[j + (size_t)i * n];
+      A[i + (size_t)j * lda] = (i == j) ? cx<double>{s * a.x, 0.0}
+                                        : cx<double>{0.5 * s * (a.x + b.x), 0.5 * s * (a.y - b.y)};
+    }
   __syncthreads();
   // Cholesky
   double prev_inv = 0.0;
@@ -51,15 +54,15 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
       break;  // uniform: every thread read the same pivot
     }
     const double invd = 1.0 / d;
-    const int m = n - k - 1;
-    for (long e = t; e < (long)m * m; e += nt) {
-      const int i = k + 1 + (int)(e % m), j = k + 1 + (int)(e / m);
-      if (i < j) continue;
-      const cx<double> lik = A[i + (size_t)k * lda], ljk = A[j + (size_t)k * lda];
-      cx<double> v = A[i + (size_t)j * lda];
-      v.x -= (lik.x * ljk.x + lik.y * ljk.y) * invd;
-      v.y -= (lik.y * ljk.x - lik.x * ljk.y) * invd;
-      A[i + (size_t)j * lda] = v;
+    for (int j = k + 1 + wave; j < n; j += nw) {
+      const cx<double> ljk = A[j + (size_t)k * lda];
+      for (int i = j + lane; i < n; i += 64) {
+        const cx<double> lik = A[i + (size_t)k * lda];
+        cx<double> v = A[i + (size_t)j * lda];
+        v.x -= (lik.x * ljk.x + lik.y * ljk.y) * invd;
+        v.y -= (lik.y * ljk.x - lik.x * ljk.y) * invd;
+        A[i + (size_t)j * lda] = v;
+      }
     }
     if (k > 0) {  // finish column k-1
       for (int i = k - 1 + t; i < n; i += nt) {
@@ -73,33 +76,30 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
   }
   __syncthreads();
   const int fail_k = failed;
-  if (fail_k == 0) {
-    for (int i = n - 1 + t; i < n; i += nt) {
-      const cx<double> v = A[i + (size_t)(n - 1) * lda];
-      A[i + (size_t)(n - 1) * lda] = {sqrt(v.x), 0.0};
-    }
+  if (fail_k == 0 && t == 0) {
+    const cx<double> v = A[(n - 1) + (size_t)(n - 1) * lda];
+    A[(n - 1) + (size_t)(n - 1) * lda] = {sqrt(v.x), 0.0};
   }
   __syncthreads();
   if (t == 0) *info = fail_k;
   if (fail_k != 0) return;
   if (Lout) {
-    for (long e = t; e < (long)n * n; e += nt) {
-      const int i = (int)(e % n), j = (int)(e / n);
-      Lout[e] = (i >= j) ? A[i + (size_t)j * lda] : cx<double>{0.0, 0.0};
-    }
+    for (int j = wave; j < n; j += nw)
+      for (int i = lane; i < n; i += 64)
+        Lout[i + (size_t)j * n] = (i >= j) ? A[i + (size_t)j * lda] : cx<double>{0.0, 0.0};
   }
   // in-place inverse of the lower triangle
   for (int k = 0; k < n; ++k) {
-    const cx<double> lkk = A[k + (size_t)k * lda];
-    const double xkk = 1.0 / lkk.x;  // diagonal is real
-    const int m = n - k - 1;
-    for (long e = t; e < (long)m * k; e += nt) {
-      const int i = k + 1 + (int)(e % m), j = (int)(e / m);
-      const cx<double> lik = A[i + (size_t)k * lda], akj = A[k + (size_t)j * lda];
-      cx<double> v = A[i + (size_t)j * lda];
-      v.x -= (lik.x * akj.x - lik.y * akj.y) * xkk;
-      v.y -= (lik.x * akj.y + lik.y * akj.x) * xkk;
-      A[i + (size_t)j * lda] = v;
+    const double xkk = 1.0 / A[k + (size_t)k * lda].x;  // diagonal is real
+    for (int j = wave; j < k; j += nw) {
+      const cx<double> akj = A[k + (size_t)j * lda];
+      for (int i = k + 1 + lane; i < n; i += 64) {
+        const cx<double> lik = A[i + (size_t)k * lda];
+        cx<double> v = A[i + (size_t)j * lda];
+        v.x -= (lik.x * akj.x - lik.y * akj.y) * xkk;
+        v.y -= (lik.x * akj.y + lik.y * akj.x) * xkk;
+        A[i + (size_t)j * lda] = v;
+      }
     }
     __syncthreads();
     for (int i = k + 1 + t; i < n; i += nt) {
@@ -114,11 +114,11 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
     __syncthreads();
   }
   // C = X^H (upper triangular)
-  for (long e = t; e < (long)n * n; e += nt) {
-    const int a = (int)(e % n), b = (int)(e / n);
-    const cx<double> x = (b >= a) ? A[b + (size_t)a * lda] : cx<double>{0.0, 0.0};
-    C[e] = {x.x, -x.y};
-  }
+  for (int b = wave; b < n; b += nw)
+    for (int a = lane; a < n; a += 64) {
+      const cx<double> x = (b >= a) ? A[b + (size_t)a * lda] : cx<double>{0.0, 0.0};
+      C[a + (size_t)b * n] = {x.x, -x.y};
+    }
 }
 
 __global__ __launch_bounds__(256) void k_chol_inv_lds(const cx<double>* __restrict__ M, int n,

@@ -31,7 +31,8 @@ constexpr double kFourPi = 12.566370614359172954;
 template <typename T>
 __global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n, double L0,
                                                       double L1, double L2, int kind, double mu,
-                                                      double g0, double coef) {
+                                                      double g0, double coef,
+                                                      const double* __restrict__ dscale) {
   const long ng = (long)n * n * n;
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= ng) return;
@@ -52,7 +53,9 @@ __global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n,
   } else {
     K = g0;
   }
-  Kt[idx] = T(coef * K);
+  // dscale (nullable): a further factor read from device memory (the upstream
+  // gradient of the energy in the backward pass), so no host round trip
+  Kt[idx] = T(coef * (dscale ? *dscale : 1.0) * K);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
@@ -183,7 +186,8 @@ template <int N, typename T>
 __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ phi, long ldphi,
                                                      const cx<T>* __restrict__ buf,
                                                      cx<T>* __restrict__ W, long ldW, int i0,
-                                                     int A, int j0, int nbc, int accumulate) {
+                                                     int A, int j0, int nbc, int accumulate,
+                                                     int sym) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   __shared__ cx<T> acc[N * 64];
@@ -200,9 +204,15 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
   // iteration (the pencil of u_ij and of phi_i) are issued before any use.
 #pragma unroll
   for (int k = 0; k < N; ++k) acc[k * 64 + t] = cx<T>{T(0), T(0)};
+  const int j = j0 + b;
   for (int a = 0; a < A; ++a) {
-    const cx<T>* src = buf + ((size_t)a + (size_t)A * b) * N * NN + off;
-    const cx<T>* fp = phi + (size_t)(i0 + a) * ldphi + off;
+    // sym: the buffer holds only the pairs i <= j of the occupied block (upper
+    // triangle, index j(j+1)/2 + i); u_ij for i > j is conj(u_ji).
+    const int i = i0 + a;
+    const size_t pidx = !sym ? (size_t)a + (size_t)A * b
+                             : (i <= j ? (size_t)j * (j + 1) / 2 + i : (size_t)i * (i + 1) / 2 + j);
+    const cx<T>* src = buf + pidx * N * NN + off;
+    const cx<T>* fp = phi + (size_t)i * ldphi + off;
     cx<T> v[N];
     cx<T> f[N];
 #pragma unroll
@@ -210,10 +220,14 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
 #pragma unroll
     for (int k = 0; k < N; ++k) f[k] = fp[k * N];
     fft_line<N, +1, T>(v);
+    if (sym && i > j) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[k].y = -v[k].y;
+    }
 #pragma unroll
     for (int k = 0; k < N; ++k) acc[k * 64 + t] = cadd(acc[k * 64 + t], cmul(f[k], v[k]));
   }
-  cx<T>* w = W + (size_t)(j0 + b) * ldW + off;
+  cx<T>* w = W + (size_t)j * ldW + off;
   if (accumulate) {
     cx<T> old[N];
 #pragma unroll
@@ -276,15 +290,17 @@ __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ 
 size_t default_pair_budget() { return (size_t)2 << 30; }
 
 template <typename T>
-ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef) {
+ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
+                             const double* dscale = nullptr) {
   const unsigned blocks = (unsigned)((g.ng + 255) / 256);
   return launch(c, "kernel_table", k_kernel_table<T>, dim3(blocks), dim3(256), 0, Kt, g.n, g.L[0],
-                g.L[1], g.L[2], g.kind, g.mu, g.g0, coef);
+                g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
 }
 
 template <int N, typename T>
 ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
-                     const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale) {
+                     const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale,
+                     const double* dscale) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
@@ -297,14 +313,38 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   int B = c->jblock > 0 ? (int)std::min<long>(nband, c->jblock) : nband;
   B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
   const int A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
+  // Pair symmetry: when psi's first n_occ orbitals are phi, u_ji = conj(u_ij)
+  // on the occupied block and only its triangle i <= j needs FFTs.  Needs the
+  // whole triangle in flight at once.
+  const long tri = (long)nocc * (nocc + 1) / 2;
+  const bool sym = c->use_symmetry && psi == phi && ldpsi == ldphi && nocc >= 2 &&
+                   tri <= maxpairs && (long)N * tri < (1L << 31);
+  const size_t pairs_alloc = std::max<size_t>((size_t)A * B, sym ? (size_t)tri : 0);
   const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
-  if ((st = ws_begin(c, kt_bytes + align_up((size_t)A * B * pair_bytes, 256))) != ACE_OK) return st;
+  if ((st = ws_begin(c, kt_bytes + align_up(pairs_alloc * pair_bytes, 256))) != ACE_OK) return st;
   T* Kt = (T*)ws_take(c, kt_bytes, &st);
-  cx<T>* buf = (cx<T>*)ws_take(c, (size_t)A * B * pair_bytes, &st);
+  cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
   if (!Kt || !buf) return st;
-  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng)) != ACE_OK) return st;
-  for (int j0 = 0; j0 < nband; j0 += B) {
+  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
+  int jstart = 0;
+  if (sym) {
+    // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
+    // accumulates all i from it (u_ij = conj(u_ji))
+    const long tri = (long)nocc * (nocc + 1) / 2;
+    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * tri)),
+                     dim3(N), 0, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) != ACE_OK)
+      return st;
+    if ((st = launch(c, "plane_kernel", k_plane_kernel<N, T>, dim3(xcd_pad((long)N * tri)),
+                     dim3(N), 0, buf, (const T*)Kt, (int)tri)) != ACE_OK)
+      return st;
+    if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nocc)),
+                     dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, 0, nocc, 0, nocc, 0,
+                     1)) != ACE_OK)
+      return st;
+    jstart = nocc;
+  }
+  for (int j0 = jstart; j0 < nband; j0 += B) {
     const int Bc = std::min(B, nband - j0);
     for (int i0 = 0; i0 < nocc; i0 += A) {
       const int Ac = std::min(A, nocc - i0);
@@ -317,7 +357,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
         return st;
       if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * Bc)),
                        dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
-                       i0 > 0 ? 1 : 0)) != ACE_OK)
+                       i0 > 0 ? 1 : 0, 0)) != ACE_OK)
         return st;
     }
   }
@@ -363,11 +403,11 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
 template <typename T>
 ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                         const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW,
-                        double scale) {
+                        double scale, const double* dscale) {
   switch (g.n) {
 #define ACE_CASE(NV) \
   case NV:           \
-    return build_W_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale);
+    return build_W_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale, dscale);
     ACE_FOR_EACH_N(ACE_CASE)
 #undef ACE_CASE
     default:
@@ -390,9 +430,11 @@ ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, in
 }
 
 template ace_status build_W_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int, long,
-                                        const cx<float>*, int, long, cx<float>*, long, double);
+                                        const cx<float>*, int, long, cx<float>*, long, double,
+                                        const double*);
 template ace_status build_W_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int, long,
-                                         const cx<double>*, int, long, cx<double>*, long, double);
+                                         const cx<double>*, int, long, cx<double>*, long, double,
+                                         const double*);
 template ace_status energy_direct_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int,
                                               long, double*);
 template ace_status energy_direct_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int,

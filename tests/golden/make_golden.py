@@ -36,6 +36,18 @@ def main():
         json.dump(out, f, indent=1)
         f.write("\n")
 
+    # 48^3, L = 20.5 bohr, 80 orbitals (seed 0), N_occ = 64: exchange energy
+    psi = synth.smooth_orbitals(48, 20.5, 80, seed=0)
+    g = O.Grid.cubic(48, 20.5)
+    out = {
+        "case": "48^3 grid, cubic L=20.5 bohr, 80 smooth orthonormal orbitals (Ecut 10 Ha, "
+                "seed 0); occupied = first 64",
+        "E_X_coulomb_nocc64": O.exchange_energy_direct(psi[:64], g),
+    }
+    with open(os.path.join(here, "smooth48_seed0.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
 
 if __name__ == "__main__":
     main()
