@@ -165,6 +165,31 @@ ace_status ace_orthonormalize(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                               const void* X, int n, long ld_x, void* Q, long ld_q,
                               int* info_dev);
 
+/*
+ * Batched build (Section 3 for many independent systems): for every instance,
+ * W = scale * V_X[phi] psi as ace_build_W, then (when xi != NULL) the
+ * compression of ace_compress with L not returned and the pivot status in
+ * *info_dev (required then).  Instances may differ in grid, cell, kernel and
+ * sizes; all share the precision.  They are spread over n_branches (1..16)
+ * concurrent streams, each with its own workspace slice, and the whole batch
+ * is captured into one HIP graph that is launched on the context stream.  A
+ * later call with an identical instance array (same pointers, sizes and
+ * settings) replays that graph without re-enqueueing; the data behind the
+ * pointers may change between calls.  Pointers must not overlap across
+ * instances' outputs.  Never synchronises.
+ */
+typedef struct {
+  ace_grid grid;
+  const void* phi; int n_occ; long ld_phi;
+  const void* psi; int n_band; long ld_psi;
+  void* W; long ld_W;
+  void* xi; long ld_xi;   /* nullable: build only */
+  int* info_dev;          /* device int, required when xi != NULL */
+  double scale;
+} ace_instance;
+ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_instance* inst,
+                             int n_branches);
+
 /* Grid sizes n (per axis) compiled into this library; returns how many were
  * written (at most cap). */
 int ace_supported_n(int* out, int cap);

@@ -14,7 +14,7 @@ ACE_COULOMB, ACE_ERFC = 0, 1
 EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
     "ace_apply", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
-    "ace_supported_n",
+    "ace_supported_n", "ace_build_batched",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
     "ace_last_error",
@@ -25,6 +25,15 @@ ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY = 0, 1, 2
 class AceGrid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("L", ctypes.c_double * 3), ("kind", ctypes.c_int),
                 ("mu", ctypes.c_double), ("g0", ctypes.c_double)]
+
+
+class AceInstance(ctypes.Structure):
+    _fields_ = [("grid", AceGrid),
+                ("phi", ctypes.c_void_p), ("n_occ", ctypes.c_int), ("ld_phi", ctypes.c_long),
+                ("psi", ctypes.c_void_p), ("n_band", ctypes.c_int), ("ld_psi", ctypes.c_long),
+                ("W", ctypes.c_void_p), ("ld_W", ctypes.c_long),
+                ("xi", ctypes.c_void_p), ("ld_xi", ctypes.c_long),
+                ("info_dev", ctypes.c_void_p), ("scale", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -45,6 +54,7 @@ _PROTOS = {
     "ace_exchange_energy_grad": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _vp, _l]),
     "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
+    "ace_build_batched": (_i, [_vp, _i, _i, ctypes.POINTER(AceInstance), _i]),
     "ace_profile_enable": (_i, [_vp, _i]),
     "ace_profile_reset": (_i, [_vp]),
     "ace_profile_count": (_i, [_vp]),

@@ -261,6 +261,41 @@ class Context:
                                                  ip))
         return out
 
+    def build_batched(self, instances, prec, n_branches: int = 4):
+        """Build W (and xi when an instance has one) for many independent systems.
+
+        ``instances``: list of dicts with keys grid (Grid), phi, psi, W, and
+        optionally xi, info (CUDA int32, required with xi) and scale.  The
+        first call captures a HIP graph; identical later calls replay it."""
+        p = _prec(prec)
+        arr = (_lib.AceInstance * len(instances))()
+        self._keep = []
+        for k, d in enumerate(instances):
+            g = d["grid"]
+            a, na, lda = _block(d["phi"], p, g.ng, "phi")
+            b, nb, ldb = _block(d["psi"], p, g.ng, "psi")
+            w, nw, ldw = _block(d["W"], p, g.ng, "W")
+            if nw != nb:
+                raise ValueError("W must hold n_band orbitals")
+            e = arr[k]
+            e.grid = g.as_c()
+            e.phi, e.n_occ, e.ld_phi = a, na, lda
+            e.psi, e.n_band, e.ld_psi = b, nb, ldb
+            e.W, e.ld_W = w, ldw
+            xi = d.get("xi")
+            if xi is not None:
+                x, nx, ldx = _block(xi, p, g.ng, "xi")
+                info = d["info"]
+                if info.dtype != torch.int32 or not info.is_cuda:
+                    raise TypeError("info must be a CUDA int32 tensor")
+                e.xi, e.ld_xi = x, ldx
+                e.info_dev = ctypes.c_void_p(info.data_ptr())
+            else:
+                e.xi, e.ld_xi, e.info_dev = None, 0, None
+            e.scale = float(d.get("scale", 1.0))
+        self._bind_stream()
+        self._check(self._lib.ace_build_batched(self._h, p, len(instances), arr, int(n_branches)))
+
     # -- profiling ------------------------------------------------------------
     def profile(self, on: bool = True):
         self._check(self._lib.ace_profile_enable(self._h, 1 if on else 0))

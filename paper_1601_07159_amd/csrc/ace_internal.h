@@ -17,6 +17,17 @@ struct ace_ctx_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_used = 0;
+  // Sub-arena (batched builds): while sub_base is set, ws_begin/ws_take carve
+  // from [sub_base, sub_base + sub_bytes) and never reallocate.
+  char* sub_base = nullptr;
+  size_t sub_bytes = 0;
+  // batched build: branch streams, fork/join events, cached graph
+  hipStream_t capture_stream = nullptr;
+  std::vector<hipStream_t> branch_streams;
+  std::vector<hipEvent_t> branch_events;
+  hipEvent_t fork_event = nullptr;
+  std::vector<unsigned char> graph_key;
+  hipGraphExec_t graph_exec = nullptr;
   size_t pair_budget = 0;  // 0 = default
   long jblock = 0;         // band block of the build; 0 = automatic
   bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
@@ -47,6 +58,21 @@ namespace ace {
 ace_status fail(ace_ctx c, ace_status s, const std::string& msg);
 ace_status hip_fail(ace_ctx c, hipError_t e, const char* where);
 
+#define ACE_TRY(x)               \
+  do {                           \
+    ace_status _s = (x);         \
+    if (_s != ACE_OK) return _s; \
+  } while (0)
+
+struct GridInfo {
+  int n;          // points per axis
+  long ng;        // n^3
+  double L[3];
+  int kind;
+  double mu, g0;
+  double omega, dV;
+};
+
 // Context workspace, a bump allocator over one device buffer.  Each entry
 // point first calls ws_begin with the total it will carve (the buffer grows if
 // needed, which synchronises the device; nothing is carved yet at that point),
@@ -56,6 +82,19 @@ ace_status ws_begin(ace_ctx c, size_t total_bytes);
 void* ws_take(ace_ctx c, size_t bytes, ace_status* st);
 // Scratch bytes gemm_cn takes from the workspace for these sizes.
 size_t gemm_cn_scratch_bytes(int na, int nb, long K);
+
+// Blocking of the build: A occupied orbitals x B bands per pair block, or the
+// symmetric occupied triangle; `bytes` is the workspace the build takes.
+struct BuildPlan {
+  int A, B;
+  bool sym;
+  size_t pairs_alloc;
+  size_t bytes;
+};
+BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t elem_bytes, int nocc, int nband,
+                     bool psi_starts_with_phi);
+// Workspace the compression takes for n_band vectors.
+size_t compress_ws_bytes(int nb, long ng);
 
 // Profiling hooks around one launch.
 void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0);
@@ -77,14 +116,6 @@ ace_status launch(ace_ctx c, const char* name, void (*kern)(KArgs...), dim3 grid
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-struct GridInfo {
-  int n;          // points per axis
-  long ng;        // n^3
-  double L[3];
-  int kind;
-  double mu, g0;
-  double omega, dV;
-};
 
 // Pair FFT stages (fft_passes.hip).
 // W = scale * (*dscale if dscale else 1) * V_X[phi] psi
@@ -95,6 +126,24 @@ ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc
 template <typename T>
 ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
                               long ldphi, double* ex_dev);
+
+// Argument checks shared by the entry points (api.hip).
+ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out);
+ace_status check_block(ace_ctx c, const void* p, int count, long ld, const GridInfo& g,
+                       const char* what);
+size_t elem_bytes(ace_prec p);
+struct Span {
+  const char* lo;
+  const char* hi;
+};
+Span span_of(const void* p, int count, long ld, long ng, size_t eb);
+bool overlap(Span a, Span b);
+
+// Compression of one instance (api.hip): M, Cholesky, xi = W L^{-H}.
+template <typename T>
+ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
+                         const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
+                         cx<double>* L_out, int* info_dev, bool mixed);
 
 // Dense stages (dense.hip).  Small matrices are complex128, column-major.
 // C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]

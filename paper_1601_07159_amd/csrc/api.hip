@@ -23,6 +23,10 @@ ace_status hip_fail(ace_ctx c, hipError_t e, const char* where) {
 ace_status ws_begin(ace_ctx c, size_t total) {
   c->ws_used = 0;
   total = align_up(total ? total : 256, 256);
+  if (c->sub_base) {
+    if (total > c->sub_bytes) return fail(c, ACE_E_NOMEM, "internal: batched workspace plan");
+    return ACE_OK;
+  }
   if (total <= c->ws_bytes) return ACE_OK;
   if (c->ws) {
     // queued kernels of earlier calls may still use the old buffer
@@ -47,13 +51,20 @@ ace_status ws_begin(ace_ctx c, size_t total) {
 
 void* ws_take(ace_ctx c, size_t bytes, ace_status* st) {
   bytes = align_up(bytes ? bytes : 256, 256);
-  if (c->ws_used + bytes > c->ws_bytes) {
+  char* base = c->sub_base ? c->sub_base : (char*)c->ws;
+  const size_t limit = c->sub_base ? c->sub_bytes : c->ws_bytes;
+  if (c->ws_used + bytes > limit) {
     *st = fail(c, ACE_E_NOMEM, "internal: workspace carve exceeds reservation");
     return nullptr;
   }
-  void* p = (char*)c->ws + c->ws_used;
+  void* p = base + c->ws_used;
   c->ws_used += bytes;
   return p;
+}
+
+size_t compress_ws_bytes(int nb, long ng) {
+  const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
+  return 3 * mat + 256 + gemm_cn_scratch_bytes(nb, nb, ng);
 }
 
 void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0) {
@@ -116,7 +127,7 @@ static bool grid_supported(int n) {
   }
 }
 
-static ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out) {
+ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out) {
   if (!g) return fail(c, ACE_E_ARG, "grid is NULL");
   if (prec != ACE_FP64 && prec != ACE_FP32 && prec != ACE_MIXED)
     return fail(c, ACE_E_ARG, "unknown precision");
@@ -142,19 +153,15 @@ static ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridIn
   return ACE_OK;
 }
 
-static size_t elem_bytes(ace_prec p) { return p == ACE_FP64 ? 16 : 8; }
+size_t elem_bytes(ace_prec p) { return p == ACE_FP64 ? 16 : 8; }
 
-struct Span {
-  const char* lo;
-  const char* hi;
-};
-static Span span_of(const void* p, int count, long ld, long ng, size_t eb) {
+Span span_of(const void* p, int count, long ld, long ng, size_t eb) {
   const char* b = (const char*)p;
   return {b, b + ((size_t)(count - 1) * ld + ng) * eb};
 }
-static bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
 
-static ace_status check_block(ace_ctx c, const void* p, int count, long ld, const GridInfo& g,
+ace_status check_block(ace_ctx c, const void* p, int count, long ld, const GridInfo& g,
                               const char* what) {
   if (!p) return fail(c, ACE_E_ARG, std::string(what) + " is NULL");
   if (count < 1) return fail(c, ACE_E_ARG, std::string(what) + ": count must be >= 1");
@@ -162,11 +169,6 @@ static ace_status check_block(ace_ctx c, const void* p, int count, long ld, cons
   return ACE_OK;
 }
 
-#define ACE_TRY(x)                   \
-  do {                               \
-    ace_status _s = (x);             \
-    if (_s != ACE_OK) return _s;     \
-  } while (0)
 
 // Cholesky failure reporting shared by compress and orthonormalize.
 static ace_status finish_info(ace_ctx c, int* info_ws, int* info_dev) {
@@ -188,11 +190,11 @@ static ace_status finish_info(ace_ctx c, int* info_ws, int* info_dev) {
 }
 
 template <typename T>
-static ace_status compress_t(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
-                             const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
-                             cx<double>* L_out, int* info_dev, bool mixed) {
+ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
+                         const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
+                         cx<double>* L_out, int* info_dev, bool mixed) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
-  ACE_TRY(ws_begin(c, 3 * mat + 256 + gemm_cn_scratch_bytes(nb, nb, g.ng)));
+  ACE_TRY(ws_begin(c, compress_ws_bytes(nb, g.ng)));
   ace_status st = ACE_OK;
   cx<double>* M = (cx<double>*)ws_take(c, mat, &st);
   cx<double>* X = (cx<double>*)ws_take(c, mat, &st);
@@ -206,6 +208,13 @@ static ace_status compress_t(ace_ctx c, const GridInfo& g, const cx<T>* psi, lon
   ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true));
   return finish_info(c, info, info_dev);
 }
+
+template ace_status compress_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, long,
+                                         const cx<float>*, long, int, cx<float>*, long,
+                                         cx<double>*, int*, bool);
+template ace_status compress_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, long,
+                                          const cx<double>*, long, int, cx<double>*, long,
+                                          cx<double>*, int*, bool);
 
 template <typename T>
 static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb, long ldxi,
@@ -308,6 +317,17 @@ ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream) {
 
 ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
   if (!c) return ACE_E_ARG;
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  for (auto s : c->branch_streams) {
+    hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+  }
+  for (auto e : c->branch_events) hipEventDestroy(e);
+  if (c->capture_stream) {
+    hipStreamSynchronize(c->capture_stream);
+    hipStreamDestroy(c->capture_stream);
+  }
+  if (c->fork_event) hipEventDestroy(c->fork_event);
   if (c->ws) {
     hipStreamSynchronize(c->stream);
     hipFree(c->ws);
@@ -412,9 +432,9 @@ ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec pre
       overlap(sx, span_of(W, n_band, ld_W, g.ng, eb)))
     return fail(c, ACE_E_ARG, "xi overlaps an input");
   if (prec == ACE_FP64)
-    return compress_t<double>(c, g, (const cx<double>*)psi, ld_psi, (const cx<double>*)W, ld_W,
+    return compress_impl<double>(c, g, (const cx<double>*)psi, ld_psi, (const cx<double>*)W, ld_W,
                               n_band, (cx<double>*)xi, ld_xi, (cx<double>*)L_out, info_dev, false);
-  return compress_t<float>(c, g, (const cx<float>*)psi, ld_psi, (const cx<float>*)W, ld_W, n_band,
+  return compress_impl<float>(c, g, (const cx<float>*)psi, ld_psi, (const cx<float>*)W, ld_W, n_band,
                            (cx<float>*)xi, ld_xi, (cx<double>*)L_out, info_dev,
                            prec == ACE_MIXED);
 }

@@ -54,14 +54,28 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
       break;  // uniform: every thread read the same pivot
     }
     const double invd = 1.0 / d;
-    for (int j = k + 1 + wave; j < n; j += nw) {
-      const cx<double> ljk = A[j + (size_t)k * lda];
-      for (int i = j + lane; i < n; i += 64) {
-        const cx<double> lik = A[i + (size_t)k * lda];
-        cx<double> v = A[i + (size_t)j * lda];
-        v.x -= (lik.x * ljk.x + lik.y * ljk.y) * invd;
-        v.y -= (lik.y * ljk.x - lik.x * ljk.y) * invd;
-        A[i + (size_t)j * lda] = v;
+    // (i, j) pairs of the trailing lower triangle, four columns per pass so
+    // that the LDS loads of a pass are independent and overlap
+    for (int j0 = k + 1 + wave; j0 < n; j0 += 4 * nw) {
+      for (int i0 = j0 + lane; i0 < n; i0 += 64) {
+        cx<double> lik[4], ljk[4], v[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u * nw, i = i0 + u * nw;
+          ok[u] = j < n && i < n;
+          const int jj = ok[u] ? j : k, ii = ok[u] ? i : k;
+          ljk[u] = A[jj + (size_t)k * lda];
+          lik[u] = A[ii + (size_t)k * lda];
+          v[u] = A[ii + (size_t)jj * lda];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (!ok[u]) continue;
+          v[u].x -= (lik[u].x * ljk[u].x + lik[u].y * ljk[u].y) * invd;
+          v[u].y -= (lik[u].y * ljk[u].x - lik[u].x * ljk[u].y) * invd;
+          A[(i0 + u * nw) + (size_t)(j0 + u * nw) * lda] = v[u];
+        }
       }
     }
     if (k > 0) {  // finish column k-1
@@ -91,14 +105,23 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
   // in-place inverse of the lower triangle
   for (int k = 0; k < n; ++k) {
     const double xkk = 1.0 / A[k + (size_t)k * lda].x;  // diagonal is real
-    for (int j = wave; j < k; j += nw) {
-      const cx<double> akj = A[k + (size_t)j * lda];
-      for (int i = k + 1 + lane; i < n; i += 64) {
-        const cx<double> lik = A[i + (size_t)k * lda];
-        cx<double> v = A[i + (size_t)j * lda];
-        v.x -= (lik.x * akj.x - lik.y * akj.y) * xkk;
-        v.y -= (lik.x * akj.y + lik.y * akj.x) * xkk;
-        A[i + (size_t)j * lda] = v;
+    for (int i = k + 1 + lane; i < n; i += 64) {
+      const cx<double> lik = A[i + (size_t)k * lda];
+      for (int j0 = wave; j0 < k; j0 += 4 * nw) {
+        cx<double> akj[4], v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u * nw < k ? j0 + u * nw : j0;
+          akj[u] = A[k + (size_t)j * lda];
+          v[u] = A[i + (size_t)j * lda];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (j0 + u * nw >= k) continue;
+          v[u].x -= (lik.x * akj[u].x - lik.y * akj[u].y) * xkk;
+          v[u].y -= (lik.x * akj[u].y + lik.y * akj[u].x) * xkk;
+          A[i + (size_t)(j0 + u * nw) * lda] = v[u];
+        }
       }
     }
     __syncthreads();
@@ -121,7 +144,7 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_chol_inv_lds(const cx<double>* __restrict__ M, int n,
+__global__ __launch_bounds__(1024) void k_chol_inv_lds(const cx<double>* __restrict__ M, int n,
                                                       double s, cx<double>* __restrict__ Lout,
                                                       cx<double>* __restrict__ C,
                                                       int* __restrict__ info,
@@ -158,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A
 ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
                     cx<double>* C, cx<double>* scratch, int* info_dev, const int* prior) {
   if (n <= kCholLdsMax)
-    return launch(c, "chol_inv_lds", k_chol_inv_lds, dim3(1), dim3(256), 0, M, n, s, Lout, C,
+    return launch(c, "chol_inv_lds", k_chol_inv_lds, dim3(1), dim3(1024), 0, M, n, s, Lout, C,
                   info_dev, prior);
   return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
                 Lout, C, info_dev, prior);

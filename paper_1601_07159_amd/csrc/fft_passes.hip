@@ -289,6 +289,36 @@ __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ 
 
 size_t default_pair_budget() { return (size_t)2 << 30; }
 
+}  // namespace
+
+BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nband,
+                     bool psi_starts_with_phi) {
+  BuildPlan pl;
+  const size_t pair_bytes = (size_t)g.ng * eb;
+  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
+  long maxpairs = (long)(budget / pair_bytes);
+  if (maxpairs < 1) maxpairs = 1;
+  // Band block B (all bands unless the tuning knob says otherwise): the
+  // accumulating pass runs (N^2 / 64) * B one-wave workgroups, each looping
+  // over the i block, and W is read-modified-written once per i block.
+  int B = c->jblock > 0 ? (int)std::min<long>(nband, c->jblock) : nband;
+  B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
+  pl.B = B;
+  pl.A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
+  // Pair symmetry: when psi's first n_occ orbitals are phi, u_ji = conj(u_ij)
+  // on the occupied block and only its triangle i <= j needs FFTs.  Needs the
+  // whole triangle in flight at once.
+  const long tri = (long)nocc * (nocc + 1) / 2;
+  pl.sym = c->use_symmetry && psi_starts_with_phi && nocc >= 2 && tri <= maxpairs &&
+           (long)g.n * tri < (1L << 31);
+  pl.pairs_alloc = std::max<size_t>((size_t)pl.A * pl.B, pl.sym ? (size_t)tri : 0);
+  pl.bytes = align_up((size_t)g.ng * std::max<size_t>(eb / 2, 4), 256) +
+             align_up(pl.pairs_alloc * pair_bytes, 256);
+  return pl;
+}
+
+namespace {
+
 template <typename T>
 ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
                              const double* dscale = nullptr) {
@@ -304,25 +334,13 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
-  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
-  long maxpairs = (long)(budget / pair_bytes);
-  if (maxpairs < 1) maxpairs = 1;
-  // Band block B (all bands unless the tuning knob says otherwise): the
-  // accumulating pass runs TILES * B one-wave workgroups, each looping over the
-  // i block, and W is read-modified-written once per i block.
-  int B = c->jblock > 0 ? (int)std::min<long>(nband, c->jblock) : nband;
-  B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
-  const int A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
-  // Pair symmetry: when psi's first n_occ orbitals are phi, u_ji = conj(u_ij)
-  // on the occupied block and only its triangle i <= j needs FFTs.  Needs the
-  // whole triangle in flight at once.
-  const long tri = (long)nocc * (nocc + 1) / 2;
-  const bool sym = c->use_symmetry && psi == phi && ldpsi == ldphi && nocc >= 2 &&
-                   tri <= maxpairs && (long)N * tri < (1L << 31);
-  const size_t pairs_alloc = std::max<size_t>((size_t)A * B, sym ? (size_t)tri : 0);
+  const BuildPlan pl = plan_build(c, g, sizeof(cx<T>), nocc, nband, psi == phi && ldpsi == ldphi);
+  const int A = pl.A, B = pl.B;
+  const bool sym = pl.sym;
+  const size_t pairs_alloc = pl.pairs_alloc;
   const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
-  if ((st = ws_begin(c, kt_bytes + align_up(pairs_alloc * pair_bytes, 256))) != ACE_OK) return st;
+  if ((st = ws_begin(c, pl.bytes)) != ACE_OK) return st;
   T* Kt = (T*)ws_take(c, kt_bytes, &st);
   cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
   if (!Kt || !buf) return st;

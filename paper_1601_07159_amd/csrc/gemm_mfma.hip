@@ -273,19 +273,36 @@ __global__ __launch_bounds__(256) void k_cn_mfma_bf16x3(const cx<float>* __restr
   }
 }
 
+// C[a + b ldc] = alpha * sum_k partial[k][b][a]: 16 threads per element, each
+// summing every 16th partial, combined in a fixed-order tree (deterministic).
 __global__ __launch_bounds__(256) void k_reduce_partials2(const cx<double>* __restrict__ partial,
                                                           int ks, int na, int nb, double alpha,
                                                           cx<double>* __restrict__ C, int ldc) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= na * nb) return;
-  const int a = idx % na, b = idx / na;
+  __shared__ double red[2][16][16];
+  const int g = threadIdx.x & 15, el = threadIdx.x >> 4;
+  const int idx = blockIdx.x * 16 + el;
   double sr = 0.0, si = 0.0;
-  for (int k = 0; k < ks; ++k) {
-    const cx<double> v = partial[(size_t)k * na * nb + idx];
-    sr += v.x;
-    si += v.y;
+  if (idx < na * nb) {
+    for (int k = g; k < ks; k += 16) {
+      const cx<double> v = partial[(size_t)k * na * nb + idx];
+      sr += v.x;
+      si += v.y;
+    }
   }
-  C[a + (size_t)b * ldc] = {alpha * sr, alpha * si};
+  red[0][el][g] = sr;
+  red[1][el][g] = si;
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if (g < w) {
+      red[0][el][g] += red[0][el][g + w];
+      red[1][el][g] += red[1][el][g + w];
+    }
+    __syncthreads();
+  }
+  if (g == 0 && idx < na * nb) {
+    const int a = idx % na, b = idx / na;
+    C[a + (size_t)b * ldc] = {alpha * red[0][el][0], alpha * red[1][el][0]};
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -409,8 +426,8 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
                      nb, K, kchunk, partial)) != ACE_OK)
       return st;
   }
-  return launch(c, "reduce_partials", k_reduce_partials2, dim3((na * nb + 255) / 256), dim3(256),
-                0, (const cx<double>*)partial, (int)ks, na, nb, alpha, C, ldc);
+  return launch(c, "reduce_partials", k_reduce_partials2, dim3((na * nb + 15) / 16), dim3(256), 0,
+                (const cx<double>*)partial, (int)ks, na, nb, alpha, C, ldc);
 }
 
 template <typename TIn, typename TAcc>

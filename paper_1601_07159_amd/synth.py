@@ -38,7 +38,7 @@ def _as3(v, cast):
 
 
 def smooth_orbitals(n, L, nband: int, seed: int, ecut: float = 10.0,
-                    orthonormal: bool = True) -> np.ndarray:
+                    orthonormal: bool = True, draw: str = "grid") -> np.ndarray:
     """Random smooth orbitals on an n0 x n1 x n2 periodic grid of an
     orthorhombic cell with edges L (bohr), complex128, shape (nband, n0, n1, n2).
 
@@ -47,6 +47,9 @@ def smooth_orbitals(n, L, nband: int, seed: int, ecut: float = 10.0,
     when ``orthonormal`` the coefficient vectors are orthonormalised by a QR
     factorisation with positive diagonal; each orbital is then
     psi_b(r) = (1/sqrt(Omega)) sum_G c_b(G) exp(i G.r).
+    draw="grid" takes normals for every grid point (those outside the sphere
+    are then zeroed); draw="sphere" takes them for the sphere's points only,
+    in C order (a cheaper stream for large batches; different orbitals).
     """
     n3 = _as3(n, int)
     L3 = _as3(L, float)
@@ -56,20 +59,36 @@ def smooth_orbitals(n, L, nband: int, seed: int, ecut: float = 10.0,
     mask = (0.5 * g2 <= ecut)
     amp = np.exp(-g2 / 8.0) * mask
     rng = np.random.default_rng(seed)
-    re = rng.standard_normal((nband,) + n3)
-    im = rng.standard_normal((nband,) + n3)
-    c = (re + 1j * im) / np.sqrt(2.0) * amp
+    if draw == "grid":
+        re = rng.standard_normal((nband,) + n3)
+        im = rng.standard_normal((nband,) + n3)
+        c = (re + 1j * im) / np.sqrt(2.0) * amp
+    elif draw == "sphere":
+        sel = mask.reshape(-1)
+        k = int(sel.sum())
+        re = rng.standard_normal((nband, k))
+        im = rng.standard_normal((nband, k))
+        c = np.zeros((nband, sel.size), dtype=np.complex128)
+        c[:, sel] = (re + 1j * im) / np.sqrt(2.0) * amp.reshape(-1)[sel]
+        c = c.reshape((nband,) + n3)
+    else:
+        raise ValueError(draw)
     if orthonormal:
-        if nband > int(mask.sum()):
+        sel = mask.reshape(-1)
+        if nband > int(sel.sum()):
             raise ValueError("more orbitals than plane waves inside the cutoff sphere")
-        q, r = np.linalg.qr(c.reshape(nband, -1).T)
+        # coefficients outside the sphere are zero: factor only the rows inside
+        q, r = np.linalg.qr(c.reshape(nband, -1)[:, sel].T)
         d = np.diag(r)
         q = q * (d / np.abs(d))[None, :]
-        c = q.T.reshape((nband,) + n3)
+        full = np.zeros((nband, sel.size), dtype=np.complex128)
+        full[:, sel] = q.T
+        c = full.reshape((nband,) + n3)
     else:
         # Keep roughly unit norm so that non-orthonormal inputs stay well scaled.
         c = c / np.sqrt(np.sum(np.abs(c) ** 2, axis=(1, 2, 3), keepdims=True))
-    psi = np.fft.ifftn(c, axes=(1, 2, 3)) * (ng / np.sqrt(omega))
+    import scipy.fft
+    psi = scipy.fft.ifftn(c, axes=(1, 2, 3), workers=-1) * (ng / np.sqrt(omega))
     return np.ascontiguousarray(psi)
 
 
@@ -126,4 +145,4 @@ def batched_instances(count: int = 48, seed: int = 1000, orbital_seed: int = 200
 
 
 def instance_orbitals(inst) -> np.ndarray:
-    return smooth_orbitals(inst["n"], inst["L"], inst["nband"], inst["seed"])
+    return smooth_orbitals(inst["n"], inst["L"], inst["nband"], inst["seed"], draw="sphere")
