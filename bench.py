@@ -34,6 +34,32 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
+FFT_SOURCES = ["paper_1601_07159_amd/csrc/fft_passes.hip", "paper_1601_07159_amd/csrc/fft_core.h"]
+
+
+def fft_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in FFT_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel, pairs_per_launch):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/hbm_traffic_<workload>.json, written from two rocprofv3 --pmc runs),
+    or None when it is missing or the FFT sources changed since it was taken."""
+    import json as _json
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = _json.load(f)
+    if d.get("source_hash") != fft_source_hash() or kernel not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][kernel]
+    return k["bytes_per_pair"] * pairs_per_launch
 
 
 def log(*a):
@@ -171,22 +197,32 @@ def main():
     #   plane_kernel:  read + write
     #   pencil_accum:  read (phi and W amortised over the pair block)
     fft_units = {"pair_fwd_slab": 1, "plane_kernel": 2, "pencil_accum": 1}
+    # pairs each pass handles per step: with the i <-> j symmetry (psi starts
+    # with phi) the forward and plane passes transform the occupied triangle
+    # plus the rectangle of extra bands; the accumulate pass reads every pair
+    sym = ctx.get_tuning("symmetry") == 1
+    transformed = (nocc * (nocc + 1) // 2 + nocc * (nband - nocc)) if sym else pairs
+    per_step = {"pair_fwd_slab": transformed, "plane_kernel": transformed, "pencil_accum": pairs}
     dom = max(fft_units, key=lambda k: prof.get(k, {"ms": 0})["ms"])
     d = prof[dom]
     avg_ms = d["ms"] / d["launches"]
-    pairs_per_launch = pairs * args.steps / d["launches"]
+    pairs_per_launch = per_step[dom] * args.steps / d["launches"]
     bytes_per_pair = fft_units[dom] * ng * sbytes
     achieved = bytes_per_pair * pairs_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom, pairs_per_launch)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 4),
-                "pairs_per_launch": pairs_per_launch}
+                "traffic": None if traffic is None else round(traffic),
+                "algorithmic_bytes_per_launch": round(bytes_per_pair * pairs_per_launch),
+                "avg_launch_ms": round(avg_ms, 4), "pairs_per_launch": pairs_per_launch}
     build_ms = st_ms["build_W"]
-    build_bytes = 4 * ng * sbytes * pairs
+    build_bytes = (3 * transformed + pairs) * ng * sbytes
     extra = {
         "stage_ms": {k: round(v, 4) for k, v in st_ms.items()},
         "build_pairs_per_s": pairs / (build_ms * 1e-3),
         "build_fft_algorithmic_GBs": build_bytes / (build_ms * 1e-3) / 1e9,
+        "build_transformed_pairs": transformed,
+        "build_roofline_ms": build_bytes / (HBM_PEAK_GBS * 1e9) * 1e3,
         "apply_tflops": 16.0 * ng * nband * nx / (st_ms["apply"] * 1e-3) / 1e12,
         "per_kernel": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 5)}
                        for k, v in prof.items()},

@@ -190,6 +190,22 @@ typedef struct {
 ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_instance* inst,
                              int n_branches);
 
+/*
+ * Autotuner of the build's blocking for one grid size and precision: times
+ * ace_build_W on scratch orbitals (n_occ of n_band, allocated and freed here,
+ * so this call allocates and synchronises) over candidate pair budgets (the
+ * number of pair spectra in flight) and band blocks, and keeps the fastest in
+ * the context; later builds of that grid size use it unless the explicit knobs
+ * are set.  cache_path (nullable): the result is appended as a text line
+ * "n element_bytes budget jblock".  Outputs (nullable): the choice and its
+ * time per build in ms.
+ */
+ace_status ace_autotune(ace_ctx ctx, const ace_grid* grid, ace_prec prec, int n_occ, int n_band,
+                        const char* cache_path, long* best_budget, long* best_jblock,
+                        double* best_ms);
+/* Load tuning results written by ace_autotune (later lines win). */
+ace_status ace_tune_load(ace_ctx ctx, const char* cache_path);
+
 /* Grid sizes n (per axis) compiled into this library; returns how many were
  * written (at most cap). */
 int ace_supported_n(int* out, int cap);
@@ -213,8 +229,11 @@ ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
  *  ACE_TUNE_SYMMETRY     1 (default): when psi's first n_occ orbitals are phi
  *                        (same pointer and ld), FFT only the pairs i <= j of the
  *                        occupied block and use u_ji = conj(u_ij); 0: all pairs
+ *  ACE_TUNE_FFT_SHAPE    line FFTs of the slab and plane passes: 1 one thread
+ *                        per line, 4 a lane quad per line, 0 (default) automatic
  * They change speed only; results agree to rounding. */
-enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2 };
+enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2,
+       ACE_TUNE_FFT_SHAPE = 3 };
 ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
 ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
 

@@ -14,12 +14,12 @@ ACE_COULOMB, ACE_ERFC = 0, 1
 EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
     "ace_apply", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
-    "ace_supported_n", "ace_build_batched",
+    "ace_supported_n", "ace_build_batched", "ace_autotune", "ace_tune_load",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
     "ace_last_error",
 ]
-ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY = 0, 1, 2
+ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE = 0, 1, 2, 3
 
 
 class AceGrid(ctypes.Structure):
@@ -55,6 +55,9 @@ _PROTOS = {
     "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
     "ace_build_batched": (_i, [_vp, _i, _i, ctypes.POINTER(AceInstance), _i]),
+    "ace_autotune": (_i, [_vp, _gp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_l),
+                          ctypes.POINTER(_l), ctypes.POINTER(_d)]),
+    "ace_tune_load": (_i, [_vp, ctypes.c_char_p]),
     "ace_profile_enable": (_i, [_vp, _i]),
     "ace_profile_reset": (_i, [_vp]),
     "ace_profile_count": (_i, [_vp]),

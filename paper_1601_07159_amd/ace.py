@@ -21,7 +21,7 @@ from ._lib import ACE_FP32, ACE_FP64, ACE_MIXED  # noqa: F401
 
 PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED}
 _TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
-              "symmetry": _lib.ACE_TUNE_SYMMETRY}
+              "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE}
 
 
 class AceError(RuntimeError):
@@ -295,6 +295,20 @@ class Context:
             e.scale = float(d.get("scale", 1.0))
         self._bind_stream()
         self._check(self._lib.ace_build_batched(self._h, p, len(instances), arr, int(n_branches)))
+
+    def autotune(self, grid: Grid, prec, n_occ: int, n_band: int, cache_path=None) -> dict:
+        """Time the build over pair budgets and band blocks; keep the fastest."""
+        g = grid.as_c()
+        bud, jb, ms = ctypes.c_long(), ctypes.c_long(), ctypes.c_double()
+        self._bind_stream()
+        self._check(self._lib.ace_autotune(
+            self._h, ctypes.byref(g), _prec(prec), int(n_occ), int(n_band),
+            cache_path.encode() if cache_path else None, ctypes.byref(bud), ctypes.byref(jb),
+            ctypes.byref(ms)))
+        return {"pair_budget": bud.value, "jblock": jb.value, "ms": ms.value}
+
+    def tune_load(self, cache_path: str):
+        self._check(self._lib.ace_tune_load(self._h, cache_path.encode()))
 
     # -- profiling ------------------------------------------------------------
     def profile(self, on: bool = True):

@@ -22,6 +22,14 @@ struct ace_ctx_s {
   char* sub_base = nullptr;
   size_t sub_bytes = 0;
   // batched build: branch streams, fork/join events, cached graph
+  // autotuned build blocking per (grid size, element bytes): {pair budget, band block}
+  struct Tuned {
+    int n;
+    int eb;
+    long budget;
+    long jblock;
+  };
+  std::vector<Tuned> tuned;
   hipStream_t capture_stream = nullptr;
   std::vector<hipStream_t> branch_streams;
   std::vector<hipEvent_t> branch_events;
@@ -31,6 +39,7 @@ struct ace_ctx_s {
   size_t pair_budget = 0;  // 0 = default
   long jblock = 0;         // band block of the build; 0 = automatic
   bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
+  int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread per line, 4 quad
   int num_cus = 256;
   std::string last_error;
   // profiling

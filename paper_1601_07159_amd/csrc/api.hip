@@ -359,6 +359,10 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
     case ACE_TUNE_PAIR_BUDGET: c->pair_budget = (size_t)value; return ACE_OK;
     case ACE_TUNE_JBLOCK: c->jblock = value; return ACE_OK;
     case ACE_TUNE_SYMMETRY: c->use_symmetry = value != 0; return ACE_OK;
+    case ACE_TUNE_FFT_SHAPE:
+      if (value != 0 && value != 1 && value != 4) return fail(c, ACE_E_ARG, "fft shape 0, 1 or 4");
+      c->fft_shape = (int)value;
+      return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }
@@ -369,6 +373,7 @@ ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
     case ACE_TUNE_PAIR_BUDGET: *value = (long)c->pair_budget; return ACE_OK;
     case ACE_TUNE_JBLOCK: *value = c->jblock; return ACE_OK;
     case ACE_TUNE_SYMMETRY: *value = c->use_symmetry ? 1 : 0; return ACE_OK;
+    case ACE_TUNE_FFT_SHAPE: *value = c->fft_shape; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }

@@ -67,6 +67,7 @@ std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_i
   std::memcpy(t + 40, &c->jblock, sizeof c->jblock);
   const int symm = c->use_symmetry ? 1 : 0;
   std::memcpy(t + 48, &symm, sizeof symm);
+  std::memcpy(t + 52, &c->fft_shape, sizeof c->fft_shape);
   return k;
 }
 

@@ -197,6 +197,12 @@ struct SmallDft<8, S, T> {
 // Radix plans.  Product of the list must equal N.
 template <int N>
 struct Plan;
+template <> struct Plan<2>   { template <template <int...> class F> using apply = F<2>; };
+template <> struct Plan<3>   { template <template <int...> class F> using apply = F<3>; };
+template <> struct Plan<4>   { template <template <int...> class F> using apply = F<4>; };
+template <> struct Plan<6>   { template <template <int...> class F> using apply = F<3, 2>; };
+template <> struct Plan<10>  { template <template <int...> class F> using apply = F<5, 2>; };
+template <> struct Plan<18>  { template <template <int...> class F> using apply = F<3, 3, 2>; };
 template <> struct Plan<8>   { template <template <int...> class F> using apply = F<8>; };
 template <> struct Plan<12>  { template <template <int...> class F> using apply = F<4, 3>; };
 template <> struct Plan<16>  { template <template <int...> class F> using apply = F<4, 4>; };
@@ -259,7 +265,104 @@ struct RadixList {
 // In-place length-N DFT of a register array.
 template <int N, int S, typename T>
 __device__ __forceinline__ void fft_line(cx<T>* v) {
-  Plan<N>::template apply<RadixList>::template run<N, S, T>(v);
+  if constexpr (N == 1) {
+    (void)v;
+  } else {
+    Plan<N>::template apply<RadixList>::template run<N, S, T>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lines split over the 4 lanes of a quad (N = 4 M).  Lane h of the quad holds
+// M values.  Two layouts:
+//   decimated  lane h holds x[h + 4 m],            m = 0..M-1
+//   block      lane h holds X[k + M kp(h)],        k = 0..M-1,
+//              kp(h) = (h >> 1) | ((h & 1) << 1)   (0, 2, 1, 3)
+// fft_quad_d2b maps decimated input to block output, fft_quad_b2d block input
+// to decimated output; both compute the unnormalised DFT of sign S.  The
+// factorisation is N = 4 x M: an M-point DFT per lane, twiddles
+// exp(S 2 pi i h k / N), and a 4-point DFT across the quad done as two
+// radix-2 exchanges through DPP quad permutations (no LDS, no barrier).
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float x) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_swap(double x) {
+  const long long u = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cx<T> quad_swap(cx<T> a) {
+  return {quad_swap<CTRL>(a.x), quad_swap<CTRL>(a.y)};
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void quad_twiddle(cx<T>* v, int h) {
+  constexpr int M = N / 4;
+#pragma unroll
+  for (int k = 1; k < M; ++k) {
+    const cx<T> w1 = root<N, S, T>(k % N);
+    const cx<T> w2 = root<N, S, T>((2 * k) % N);
+    const cx<T> w3 = root<N, S, T>((3 * k) % N);
+    const cx<T> w = h == 0 ? cx<T>{T(1), T(0)} : h == 1 ? w1 : h == 2 ? w2 : w3;
+    v[k] = cmul(v[k], w);
+  }
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_quad_d2b(cx<T>* v, int h) {
+  constexpr int M = N / 4;
+  static_assert(N % 4 == 0, "quad lines need N divisible by 4");
+  fft_line<M, S, T>(v);
+  quad_twiddle<N, S, T>(v, h);
+  const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^2: (u, w) -> (u + w, u - w)
+    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    v[k] = hi ? csub(p, v[k]) : cadd(v[k], p);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^1: (u, w) -> (u + t w, u - t w), t = (S i)^(h >> 1)
+    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    const cx<T> q = odd ? v[k] : p;
+    const cx<T> r = odd ? p : v[k];
+    const cx<T> tq = hi ? mul_si<S>(q) : q;
+    v[k] = odd ? csub(r, tq) : cadd(r, tq);
+  }
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_quad_b2d(cx<T>* v, int h) {
+  constexpr int M = N / 4;
+  static_assert(N % 4 == 0, "quad lines need N divisible by 4");
+  const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes L, L^1 hold X[c], X[c + 2]: sum and difference
+    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    v[k] = odd ? csub(p, v[k]) : cadd(v[k], p);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes L, L^2: the odd pair carries the factor S i
+    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    const cx<T> q = hi ? v[k] : p;
+    const cx<T> r = hi ? p : v[k];
+    const cx<T> wq = odd ? mul_si<S>(q) : q;
+    v[k] = hi ? csub(r, wq) : cadd(r, wq);
+  }
+  quad_twiddle<N, S, T>(v, h);
+  fft_line<M, S, T>(v);
+}
+
+// block position of value k on lane h
+__device__ __forceinline__ int quad_block_index(int k, int M, int h) {
+  return k + M * (((h >> 1) | ((h & 1) << 1)));
 }
 
 }  // namespace ace

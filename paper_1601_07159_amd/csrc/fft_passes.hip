@@ -88,9 +88,12 @@ __device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0
   }
 }
 
+// One-thread-per-line variants of the slab and plane passes (a workgroup of N
+// threads, each owning a whole row or column in registers).
+
 // Forward slab pass: one workgroup of N threads per (x0, pair).
 template <int N, typename T>
-__global__ __launch_bounds__(N) void k_pair_fwd_slab(const cx<T>* __restrict__ phi, long ldphi,
+__global__ __launch_bounds__(N) void k_pair_fwd_slab_t1(const cx<T>* __restrict__ phi, long ldphi,
                                                      const cx<T>* __restrict__ psi, long ldpsi,
                                                      cx<T>* __restrict__ buf, int mode, int i0,
                                                      int A, int j0, long p0, int npairs) {
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(N) void k_pair_fwd_slab(const cx<T>* __restrict__ p
 // LDS: forward FFT along axis 0, multiply by K', inverse FFT along axis 0, then
 // inverse FFT along axis 2.  Loads and stores are contiguous N-wide rows.
 template <int N, typename T>
-__global__ __launch_bounds__(N) void k_plane_kernel(cx<T>* __restrict__ buf,
+__global__ __launch_bounds__(N) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
                                                     const T* __restrict__ Kt, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
@@ -174,6 +177,111 @@ __global__ __launch_bounds__(N) void k_plane_kernel(cx<T>* __restrict__ buf,
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < N; ++r) plane[(size_t)r * NN + t] = s[r * LD + t];
+}
+
+// The slab and plane passes split every line FFT over the 4 lanes of a quad
+// (fft_quad_*): a workgroup of 4N threads handles an N x N slab or plane (line
+// l = t / 4, quad lane h = t % 4).  LDS rows are kQuadLd(N) elements apart with
+// kQuadLd = 4 (mod 16): a 16-lane phase of an 8-byte access then touches 4
+// lines x 4 quad lanes in distinct banks, for row reads (l LD + h + 4m) and
+// column reads ((h + 4m) LD + l) alike.
+template <int N>
+constexpr int kQuadLd = N + ((4 - N % 16) + 16) % 16;
+
+// Forward slab pass: one workgroup per (x0 slab, pair).  The pair product
+// conj(phi_i) psi_j is formed while the slab is loaded (coalesced) into LDS;
+// 2-D FFT over axis 2 (rows) then axis 1 (columns); the column results go
+// straight to global memory, lanes on consecutive columns.
+template <int N, typename T>
+__global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict__ phi, long ldphi,
+                                                         const cx<T>* __restrict__ psi, long ldpsi,
+                                                         cx<T>* __restrict__ buf, int mode, int i0,
+                                                         int A, int j0, long p0, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kQuadLd<N>;
+  constexpr int M = N / 4;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int x0 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)x0 * npairs);
+  int i, j;
+  pair_of(mode, i0, A, j0, p0, p, &i, &j);
+  const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
+  const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
+  const int t = threadIdx.x;
+  const int l = t >> 2, h = t & 3;
+  const int rr = t / N, cc = t - rr * N;  // element t + 4N q sits at row 4q + rr, column cc
+  {
+    cx<T> va[M], vb[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) va[q] = a[(4 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) vb[q] = b[(4 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) s[(4 * q + rr) * LD + cc] = cmulc(va[q], vb[q]);
+  }
+  __syncthreads();
+  cx<T> v[M];
+  // axis 2: row l
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
+  fft_quad_d2b<N, -1, T>(v, h);
+#pragma unroll
+  for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
+  __syncthreads();
+  // axis 1: column l
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[(h + 4 * m) * LD + l];
+  fft_quad_d2b<N, -1, T>(v, h);
+  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
+#pragma unroll
+  for (int k = 0; k < M; ++k) out[quad_block_index(k, M, h) * N] = v[k];
+}
+
+// Plane pass: one workgroup per (k1 plane, pair).  Along axis 0 (column l of
+// the plane, read straight from global memory): forward FFT, multiply by K',
+// inverse FFT; then through LDS the inverse FFT along axis 2 (row l); coalesced
+// store of the plane.
+template <int N, typename T>
+__global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
+                                                        const T* __restrict__ Kt, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kQuadLd<N>;
+  constexpr int M = N / 4;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int k1 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)k1 * npairs);
+  const int t = threadIdx.x;
+  const int l = t >> 2, h = t & 3;
+  cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
+  cx<T> v[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + l];
+  fft_quad_d2b<N, -1, T>(v, h);
+  const T* kcol = Kt + (size_t)k1 * N + l;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T kk = kcol[(size_t)quad_block_index(k, M, h) * NN];
+    v[k].x *= kk;
+    v[k].y *= kk;
+  }
+  fft_quad_b2d<N, +1, T>(v, h);
+#pragma unroll
+  for (int m = 0; m < M; ++m) s[(h + 4 * m) * LD + l] = v[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
+  fft_quad_d2b<N, +1, T>(v, h);
+  // row l is read and rewritten by its own quad only (one wave, in order)
+#pragma unroll
+  for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
+  __syncthreads();
+  const int rr = t / N, cc = t - rr * N;
+#pragma unroll
+  for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
 }
 
 // Pencil pass with accumulation: one thread per (x0, x2) pencil along axis 1,
@@ -240,35 +348,43 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
   }
 }
 
-// Energy pencil pass: forward FFT along axis 0 and sum_G K |rho^(G)|^2 for the
-// pencil; one partial per 64-pencil tile, weighted 2 for i < j (the j, i pair
-// has the same sum because K(G) = K(-G)).
+// Energy pencil pass: forward FFT along axis 0 and sum_G K |rho^(G)|^2 over 64
+// pencils per workgroup; one partial per workgroup, weighted 2 for i < j (the
+// pair j, i has the same sum because K(G) = K(-G)).
 template <int N, typename T>
-__global__ __launch_bounds__(64) void k_pencil_energy(const cx<T>* __restrict__ buf,
-                                                      const T* __restrict__ Kt, long p0,
-                                                      double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_pencil_energy(const cx<T>* __restrict__ buf,
+                                                       const T* __restrict__ Kt, long p0,
+                                                       double* __restrict__ partial) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
+  constexpr int M = N / 4;
+  __shared__ double red[4];
   const int p = blockIdx.x / TILES;
-  const int q = (blockIdx.x - p * TILES) * 64 + threadIdx.x;
+  const int tile = blockIdx.x - p * TILES;
+  const int t = threadIdx.x;
+  const int h = t & 3;
+  const int q = tile * 64 + (t >> 2);
   double sum = 0.0;
   if (q < NN) {
     const cx<T>* base = buf + (size_t)p * N * NN + q;
-    cx<T> v[N];
+    cx<T> v[M];
 #pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = base[(size_t)k * NN];
-    fft_line<N, -1, T>(v);
+    for (int m = 0; m < M; ++m) v[m] = base[(size_t)(h + 4 * m) * NN];
+    fft_quad_d2b<N, -1, T>(v, h);
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const double kk = (double)Kt[k * NN + q];
+    for (int k = 0; k < M; ++k) {
+      const double kk = (double)Kt[(size_t)quad_block_index(k, M, h) * NN + q];
       sum += kk * ((double)v[k].x * v[k].x + (double)v[k].y * v[k].y);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
-  if (threadIdx.x == 0) {
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+  if ((t & 63) == 0) red[t >> 6] = sum;
+  __syncthreads();
+  if (t == 0) {
     int i, j;
     pair_of(1, 0, 1, 0, p0, p, &i, &j);
-    partial[(size_t)(p0 + p) * TILES + (blockIdx.x - p * TILES)] = (i == j ? 1.0 : 2.0) * sum;
+    partial[(size_t)(p0 + p) * TILES + tile] =
+        (i == j ? 1.0 : 2.0) * ((red[0] + red[1]) + (red[2] + red[3]));
   }
 }
 
@@ -295,22 +411,33 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
                      bool psi_starts_with_phi) {
   BuildPlan pl;
   const size_t pair_bytes = (size_t)g.ng * eb;
-  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
+  // explicit knobs first, then an autotuned entry for this grid size, then defaults
+  size_t budget = c->pair_budget;
+  long jblock = c->jblock;
+  for (const auto& t : c->tuned)
+    if (t.n == g.n && t.eb == (int)eb) {
+      if (!budget) budget = (size_t)t.budget;
+      if (!jblock) jblock = t.jblock;
+    }
+  if (!budget) budget = default_pair_budget();
   long maxpairs = (long)(budget / pair_bytes);
   if (maxpairs < 1) maxpairs = 1;
-  // Band block B (all bands unless the tuning knob says otherwise): the
-  // accumulating pass runs (N^2 / 64) * B one-wave workgroups, each looping
-  // over the i block, and W is read-modified-written once per i block.
-  int B = c->jblock > 0 ? (int)std::min<long>(nband, c->jblock) : nband;
-  B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
-  pl.B = B;
-  pl.A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
+  // Band block B (all bands unless tuned otherwise): the accumulating pass runs
+  // (N^2 / 64) * B one-wave workgroups, each looping over the i block, and W is
+  // read-modified-written once per i block.
   // Pair symmetry: when psi's first n_occ orbitals are phi, u_ji = conj(u_ij)
   // on the occupied block and only its triangle i <= j needs FFTs.  Needs the
   // whole triangle in flight at once.
   const long tri = (long)nocc * (nocc + 1) / 2;
   pl.sym = c->use_symmetry && psi_starts_with_phi && nocc >= 2 && tri <= maxpairs &&
            (long)g.n * tri < (1L << 31);
+  // the rectangular blocks cover the bands after the triangle (all of them
+  // without symmetry)
+  const int nrect = std::max(1, pl.sym ? nband - nocc : nband);
+  int B = jblock > 0 ? (int)std::min<long>(nrect, jblock) : nrect;
+  B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
+  pl.B = B;
+  pl.A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
   pl.pairs_alloc = std::max<size_t>((size_t)pl.A * pl.B, pl.sym ? (size_t)tri : 0);
   pl.bytes = align_up((size_t)g.ng * std::max<size_t>(eb / 2, 4), 256) +
              align_up(pl.pairs_alloc * pair_bytes, 256);
@@ -325,6 +452,35 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
   const unsigned blocks = (unsigned)((g.ng + 255) / 256);
   return launch(c, "kernel_table", k_kernel_table<T>, dim3(blocks), dim3(256), 0, Kt, g.n, g.L[0],
                 g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
+}
+
+// Line shape of the slab and plane passes: one thread per line (better for
+// FP32) or a quad per line (far fewer registers; no spills for FP64 at large
+// N).  The tuning knob ACE_TUNE_FFT_SHAPE overrides: 1 = thread, 4 = quad.
+template <int N, typename T>
+bool use_quad(ace_ctx c) {
+  if (c->fft_shape == 1) return false;
+  if (c->fft_shape == 4) return true;
+  return sizeof(T) == 8 && N >= 48;
+}
+
+template <int N, typename T>
+ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx<T>* psi,
+                    long ldpsi, cx<T>* buf, int mode, int i0, int A, int j0, long p0, int np) {
+  const dim3 grid(xcd_pad((long)N * np));
+  if (quad)
+    return launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, grid, dim3(4 * N), 0, phi, ldphi, psi,
+                  ldpsi, buf, mode, i0, A, j0, p0, np);
+  return launch(c, "pair_fwd_slab", k_pair_fwd_slab_t1<N, T>, grid, dim3(N), 0, phi, ldphi, psi,
+                ldpsi, buf, mode, i0, A, j0, p0, np);
+}
+
+template <int N, typename T>
+ace_status plane(ace_ctx c, bool quad, cx<T>* buf, const T* Kt, int np) {
+  const dim3 grid(xcd_pad((long)N * np));
+  if (quad)
+    return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, Kt, np);
+  return launch(c, "plane_kernel", k_plane_kernel_t1<N, T>, grid, dim3(N), 0, buf, Kt, np);
 }
 
 template <int N, typename T>
@@ -345,17 +501,16 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
   if (!Kt || !buf) return st;
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
+  const bool quad = use_quad<N, T>(c);
   int jstart = 0;
   if (sym) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
     // accumulates all i from it (u_ij = conj(u_ji))
     const long tri = (long)nocc * (nocc + 1) / 2;
-    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * tri)),
-                     dim3(N), 0, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) != ACE_OK)
+    if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) !=
+        ACE_OK)
       return st;
-    if ((st = launch(c, "plane_kernel", k_plane_kernel<N, T>, dim3(xcd_pad((long)N * tri)),
-                     dim3(N), 0, buf, (const T*)Kt, (int)tri)) != ACE_OK)
-      return st;
+    if ((st = plane<N, T>(c, quad, buf, Kt, (int)tri)) != ACE_OK) return st;
     if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nocc)),
                      dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, 0, nocc, 0, nocc, 0,
                      1)) != ACE_OK)
@@ -367,12 +522,10 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
     for (int i0 = 0; i0 < nocc; i0 += A) {
       const int Ac = std::min(A, nocc - i0);
       const int np = Ac * Bc;
-      if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * np)),
-                       dim3(N), 0, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) != ACE_OK)
+      if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) !=
+          ACE_OK)
         return st;
-      if ((st = launch(c, "plane_kernel", k_plane_kernel<N, T>, dim3(xcd_pad((long)N * np)),
-                       dim3(N), 0, buf, (const T*)Kt, np)) != ACE_OK)
-        return st;
+      if ((st = plane<N, T>(c, quad, buf, Kt, np)) != ACE_OK) return st;
       if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * Bc)),
                        dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
                        i0 > 0 ? 1 : 0, 0)) != ACE_OK)
@@ -405,10 +558,10 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
   for (long p0 = 0; p0 < total; p0 += chunk) {
     const int np = (int)std::min(chunk, total - p0);
-    if ((st = launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, dim3(xcd_pad((long)N * np)),
-                     dim3(N), 0, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0, np)) != ACE_OK)
+    if ((st = fwd_slab<N, T>(c, use_quad<N, T>(c), phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
+                             np)) != ACE_OK)
       return st;
-    if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(64), 0,
+    if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(256), 0,
                      (const cx<T>*)buf, (const T*)Kt, p0, partial)) != ACE_OK)
       return st;
   }

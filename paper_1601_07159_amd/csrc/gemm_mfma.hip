@@ -343,27 +343,36 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
     }
     __syncthreads();
     const int steps = (na - ac) < 64 ? (na - ac + 3) / 4 : 16;
-    for (int st = 0; st < steps; ++st) {
-      const int a = ac + 4 * st + kq;
-      TAcc xr[2], xi[2];
+    // four 4-orbital steps per group: all their A loads are issued first
+    for (int st0 = 0; st0 < steps; st0 += 4) {
+      TAcc xr[4][2], xi[4][2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        const long r = rt0 + 16 * x + r16;
-        cx<TIn> v = {TIn(0), TIn(0)};
-        if (a < na && r < K) v = A[(size_t)a * lda + r];
-        xr[x] = (TAcc)v.x;
-        xi[x] = (TAcc)v.y;
-      }
-#pragma unroll
-      for (int y = 0; y < NBB; ++y) {
-        const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
-        const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
+      for (int u = 0; u < 4; ++u) {
+        const int a = ac + 4 * (st0 + u) + kq;
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          yre[x][y] = mfma4(xr[x], cr, yre[x][y]);
-          yre[x][y] = mfma4(xi[x], -ci, yre[x][y]);
-          yim[x][y] = mfma4(xr[x], ci, yim[x][y]);
-          yim[x][y] = mfma4(xi[x], cr, yim[x][y]);
+          const long r = rt0 + 16 * x + r16;
+          cx<TIn> v = {TIn(0), TIn(0)};
+          if (st0 + u < steps && a < na && r < K) v = A[(size_t)a * lda + r];
+          xr[u][x] = (TAcc)v.x;
+          xi[u][x] = (TAcc)v.y;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (st0 + u >= steps) break;
+        const int st = st0 + u;
+#pragma unroll
+        for (int y = 0; y < NBB; ++y) {
+          const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
+          const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            yre[x][y] = mfma4(xr[u][x], cr, yre[x][y]);
+            yre[x][y] = mfma4(xi[u][x], -ci, yre[x][y]);
+            yim[x][y] = mfma4(xr[u][x], ci, yim[x][y]);
+            yim[x][y] = mfma4(xi[u][x], cr, yim[x][y]);
+          }
         }
       }
     }

@@ -1,0 +1,144 @@
+// Autotuner of the build's blocking: for one grid size and precision it times
+// the build over candidate pair budgets (how many pair spectra are in flight,
+// i.e. the pair-batch width) and band blocks on scratch orbitals, keeps the
+// fastest in the context, and optionally appends it to a text cache file
+// ("n elem_bytes budget jblock" per line) that ace_tune_load reads back.
+#include <cstdio>
+#include <vector>
+
+#include "ace_internal.h"
+
+#define ACE_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace ace {
+namespace {
+
+// Smooth, finite scratch orbitals: a few plane waves per orbital.
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_scratch(cx<T>* x, int n, int count) {
+  const long ng = (long)n * n * n;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= ng * count) return;
+  const int b = (int)(idx / ng);
+  const long r = idx - (long)b * ng;
+  const int x2 = (int)(r % n), x1 = (int)((r / n) % n), x0 = (int)(r / ((long)n * n));
+  const double ph = 6.283185307179586 * ((b % 5 + 1) * x0 + (b % 3) * x1 + (b % 7) * x2) / n;
+  x[idx] = {T(cos(ph) * (1.0 + 0.1 * b)), T(sin(ph))};
+}
+
+void upsert(ace_ctx c, int n, int eb, long budget, long jblock) {
+  for (auto& t : c->tuned)
+    if (t.n == n && t.eb == eb) {
+      t.budget = budget;
+      t.jblock = jblock;
+      return;
+    }
+  c->tuned.push_back({n, eb, budget, jblock});
+}
+
+}  // namespace
+}  // namespace ace
+
+using namespace ace;
+
+ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec prec, int n_occ,
+                                   int n_band, const char* cache_path, long* best_budget,
+                                   long* best_jblock, double* best_ms) {
+  if (!c) return ACE_E_ARG;
+  GridInfo g;
+  ACE_TRY(check_grid(c, grid, prec, &g));
+  if (n_occ < 1 || n_band < n_occ) return fail(c, ACE_E_ARG, "need 1 <= n_occ <= n_band");
+  const size_t eb = elem_bytes(prec);
+  void* psi = nullptr;
+  void* W = nullptr;
+  hipError_t e = hipMalloc(&psi, (size_t)n_band * g.ng * eb);
+  if (e == hipSuccess) e = hipMalloc(&W, (size_t)n_band * g.ng * eb);
+  if (e != hipSuccess) {
+    if (psi) hipFree(psi);
+    (void)hipGetLastError();
+    return fail(c, ACE_E_NOMEM, "autotune scratch allocation");
+  }
+  const long total = (long)n_band * g.ng;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  ace_status st = prec == ACE_FP64
+                      ? launch(c, "fill_scratch", k_fill_scratch<double>, dim3(blocks), dim3(256), 0,
+                               (cx<double>*)psi, g.n, n_band)
+                      : launch(c, "fill_scratch", k_fill_scratch<float>, dim3(blocks), dim3(256), 0,
+                               (cx<float>*)psi, g.n, n_band);
+  const size_t save_budget = c->pair_budget;
+  const long save_jblock = c->jblock;
+  const bool save_prof = c->profiling;
+  c->profiling = false;
+  const long budgets[] = {256L << 20, 512L << 20, 1L << 30, 2L << 30, 4L << 30, 8L << 30};
+  std::vector<long> jblocks = {0};
+  if (n_band >= 32) jblocks.push_back((n_band + 1) / 2);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  double best = 1e300;
+  long bb = 0, bj = 0;
+  const size_t pair_bytes = (size_t)g.ng * eb;
+  for (long bud : budgets) {
+    if (st != ACE_OK) break;
+    // skip budgets that change nothing: larger than every pair at once
+    if ((size_t)bud / 2 >= pair_bytes * (size_t)n_occ * n_band && bud != budgets[0]) continue;
+    for (long jb : jblocks) {
+      c->pair_budget = (size_t)bud;
+      c->jblock = jb;
+      auto run = [&]() {
+        return prec == ACE_FP64
+                   ? build_W_impl<double>(c, g, (const cx<double>*)psi, n_occ, g.ng,
+                                          (const cx<double>*)psi, n_band, g.ng, (cx<double>*)W,
+                                          g.ng, 1.0)
+                   : build_W_impl<float>(c, g, (const cx<float>*)psi, n_occ, g.ng,
+                                         (const cx<float>*)psi, n_band, g.ng, (cx<float>*)W, g.ng,
+                                         1.0);
+      };
+      if ((st = run()) != ACE_OK) break;  // warm-up (and workspace growth)
+      float ms = 0.f;
+      hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 3 && st == ACE_OK; ++r) st = run();
+      hipEventRecord(e1, c->stream);
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&ms, e0, e1);
+      if (st == ACE_OK && ms / 3.0 < best) {
+        best = ms / 3.0;
+        bb = bud;
+        bj = jb;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->pair_budget = save_budget;
+  c->jblock = save_jblock;
+  c->profiling = save_prof;
+  hipStreamSynchronize(c->stream);
+  hipFree(psi);
+  hipFree(W);
+  if (st != ACE_OK) return st;
+  upsert(c, g.n, (int)eb, bb, bj);
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%d %d %ld %ld\n", g.n, (int)eb, bb, bj);
+      fclose(f);
+    }
+  }
+  if (best_budget) *best_budget = bb;
+  if (best_jblock) *best_jblock = bj;
+  if (best_ms) *best_ms = best;
+  return ACE_OK;
+}
+
+ACE_EXPORT ace_status ace_tune_load(ace_ctx c, const char* cache_path) {
+  if (!c || !cache_path) return ACE_E_ARG;
+  FILE* f = fopen(cache_path, "r");
+  if (!f) return fail(c, ACE_E_ARG, "cannot open tuning cache");
+  int n, eb;
+  long bud, jb;
+  while (fscanf(f, "%d %d %ld %ld", &n, &eb, &bud, &jb) == 4)
+    if (n > 0 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0) upsert(c, n, eb, bud, jb);
+  fclose(f);
+  return ACE_OK;
+}
