@@ -164,11 +164,12 @@ template <typename T>
 ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
                    int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate);
 // Fused: A = s (M + M^H)/2, A = L L^H, Lout = L (nullable), C = L^{-H}.
-// scratch: n x n complex128 (used when n is too large for LDS).  info_dev gets
+// scratch: chol_scratch_elems(n) complex128 (used when n > 88).  info_dev gets
 // 0 or the first failing pivot; a nonzero *prior (nullable) is propagated.
 ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
                     cx<double>* C, cx<double>* scratch, int* info_dev,
                     const int* prior = nullptr);
+inline size_t chol_scratch_elems(int n) { return (size_t)n * n + (size_t)16 * n; }
 // *out = s * sum |A_ij|^2 over an m x n column-major block
 ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out);
 

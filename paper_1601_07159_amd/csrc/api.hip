@@ -64,7 +64,8 @@ void* ws_take(ace_ctx c, size_t bytes, ace_status* st) {
 
 size_t compress_ws_bytes(int nb, long ng) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
-  return 3 * mat + 256 + gemm_cn_scratch_bytes(nb, nb, ng);
+  const size_t scr = align_up(chol_scratch_elems(nb) * sizeof(cx<double>), 256);
+  return 2 * mat + scr + 256 + gemm_cn_scratch_bytes(nb, nb, ng);
 }
 
 void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0) {
@@ -197,7 +198,7 @@ ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ld
   ACE_TRY(ws_begin(c, compress_ws_bytes(nb, g.ng)));
   ace_status st = ACE_OK;
   cx<double>* M = (cx<double>*)ws_take(c, mat, &st);
-  cx<double>* X = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* X = (cx<double>*)ws_take(c, chol_scratch_elems(nb) * sizeof(cx<double>), &st);
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   int* info = (int*)ws_take(c, 256, &st);
   if (!M || !X || !C || !info) return st;
@@ -245,10 +246,11 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
                          long ldq, int* info_dev) {
   const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
   const size_t tmp = align_up((size_t)n * g.ng * sizeof(cx<T>), 256);
-  ACE_TRY(ws_begin(c, 3 * mat + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, g.ng)));
+  const size_t scr = align_up(chol_scratch_elems(n) * sizeof(cx<double>), 256);
+  ACE_TRY(ws_begin(c, 2 * mat + scr + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, g.ng)));
   ace_status st = ACE_OK;
   cx<double>* S = (cx<double>*)ws_take(c, mat, &st);
-  cx<double>* Xs = (cx<double>*)ws_take(c, mat, &st);
+  cx<double>* Xs = (cx<double>*)ws_take(c, scr, &st);
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   int* info1 = (int*)ws_take(c, 256, &st);
   int* info2 = (int*)ws_take(c, 256, &st);

@@ -11,25 +11,41 @@ namespace ace {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Fused factorisation of a small Hermitian matrix, one workgroup:
-//   A = s (M + M^H)/2  (lower triangle),  A = L L^H  (Cholesky, right-looking),
-//   optional copy of L,  X = L^{-1} in place,  C = X^H = L^{-H}.
-// Cholesky step k updates the trailing lower triangle with the unscaled column
-// k divided by the pivot, and in the same phase finishes column k-1 (scale by
-// 1/sqrt(pivot)); columns touched in one phase are disjoint, so one barrier per
-// step suffices.  The in-place inverse eliminates column by column:
-//   x_kk = 1/l_kk, rows below k of the left block get the rank-1 update with
-//   the column -l_ik x_kk, then column k and row k are scaled.
-// `A` points to LDS (n <= kCholLdsMax) or to a global scratch matrix; lda >= n.
-constexpr int kCholLdsMax = 88;
+// Fused factorisation of a Hermitian matrix, one workgroup:
+//   A = s (M + M^H)/2  (lower triangle),  A = L L^H  (Cholesky),
+//   optional copy of L,  C = L^{-H}  (upper triangular).
+// This form serves n above kCholRegMax (the register form below covers the
+// smaller ones), with A in global scratch.  Blocked in panels of kCholNB columns so that only a few workgroup barriers
+// are needed per panel:
+//   Cholesky  the diagonal block is factored by wave 0 alone (lanes of one
+//             wave stay ordered without barriers), the rows below solve
+//             x L_kk^H = a one thread per row, the trailing lower triangle is
+//             updated with kCholNB-term dot products.
+//   inverse   X = L^{-1}: diagonal blocks inverted in place, one wave each;
+//             then block row i: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj, with the
+//             finished blocks of X kept (conjugate-transposed) in C.
+// lda >= n; T is scratch of kCholNB x n.
+constexpr int kCholNB = 16;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ cx<double> cmul_d(cx<double> a, cx<double> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+__device__ __forceinline__ cx<double> cmulcj_d(cx<double> a, cx<double> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
 
 __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, int n, double s,
-                                              cx<double>* A, int lda,
+                                              cx<double>* A, int lda, cx<double>* T,
                                               cx<double>* __restrict__ Lout,
                                               cx<double>* __restrict__ C, int* __restrict__ info,
                                               const int* __restrict__ prior) {
-  // Element loops: waves stride over columns, lanes over rows (consecutive
-  // rows are consecutive in memory), so no integer division is needed.
+  constexpr int NB = kCholNB;
   __shared__ int failed;
   const int t = threadIdx.x, nt = blockDim.x;
   const int lane = t & 63, wave = t >> 6, nw = nt >> 6;
@@ -45,56 +61,77 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
                                         : cx<double>{0.5 * s * (a.x + b.x), 0.5 * s * (a.y - b.y)};
     }
   __syncthreads();
-  // Cholesky
-  double prev_inv = 0.0;
-  for (int k = 0; k < n; ++k) {
-    const double d = A[k + (size_t)k * lda].x;
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (t == 0) failed = k + 1;
-      break;  // uniform: every thread read the same pivot
-    }
-    const double invd = 1.0 / d;
-    // (i, j) pairs of the trailing lower triangle, four columns per pass so
-    // that the LDS loads of a pass are independent and overlap
-    for (int j0 = k + 1 + wave; j0 < n; j0 += 4 * nw) {
-      for (int i0 = j0 + lane; i0 < n; i0 += 64) {
-        cx<double> lik[4], ljk[4], v[4];
-        bool ok[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = j0 + u * nw, i = i0 + u * nw;
-          ok[u] = j < n && i < n;
-          const int jj = ok[u] ? j : k, ii = ok[u] ? i : k;
-          ljk[u] = A[jj + (size_t)k * lda];
-          lik[u] = A[ii + (size_t)k * lda];
-          v[u] = A[ii + (size_t)jj * lda];
+
+  // ---- Cholesky, right-looking by panels
+  for (int kb = 0; kb < n; kb += NB) {
+    const int nb = n - kb < NB ? n - kb : NB;
+    if (wave == 0) {
+      for (int k = kb; k < kb + nb; ++k) {
+        const double d = A[k + (size_t)k * lda].x;
+        if (!(d > 0.0) || !isfinite(d)) {
+          if (lane == 0) failed = k + 1;
+          break;  // uniform across the wave
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (!ok[u]) continue;
-          v[u].x -= (lik[u].x * ljk[u].x + lik[u].y * ljk[u].y) * invd;
-          v[u].y -= (lik[u].y * ljk[u].x - lik[u].x * ljk[u].y) * invd;
-          A[(i0 + u * nw) + (size_t)(j0 + u * nw) * lda] = v[u];
+        const double r = sqrt(d), inv = 1.0 / r;
+        wave_sync();
+        if (lane == 0) A[k + (size_t)k * lda] = {r, 0.0};
+        const int i = k + 1 + lane;
+        if (i < kb + nb) {
+          const cx<double> v = A[i + (size_t)k * lda];
+          A[i + (size_t)k * lda] = {v.x * inv, v.y * inv};
         }
+        wave_sync();
+        const int m = kb + nb - k - 1;
+        for (int e = lane; e < m * m; e += 64) {
+          const int ii = k + 1 + e % m, jj = k + 1 + e / m;
+          if (ii < jj) continue;
+          const cx<double> u = cmulcj_d(A[ii + (size_t)k * lda], A[jj + (size_t)k * lda]);
+          cx<double> v = A[ii + (size_t)jj * lda];
+          A[ii + (size_t)jj * lda] = {v.x - u.x, v.y - u.y};
+        }
+        wave_sync();
       }
     }
-    if (k > 0) {  // finish column k-1
-      for (int i = k - 1 + t; i < n; i += nt) {
-        cx<double> v = A[i + (size_t)(k - 1) * lda];
-        A[i + (size_t)(k - 1) * lda] =
-            (i == k - 1) ? cx<double>{sqrt(v.x), 0.0} : cx<double>{v.x * prev_inv, v.y * prev_inv};
+    __syncthreads();
+    if (failed) break;
+    // rows below the diagonal block: x L_kk^H = a, one thread per row
+    for (int i = kb + nb + t; i < n; i += nt) {
+      cx<double> x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = c < nb ? A[i + (size_t)(kb + c) * lda] : cx<double>{0, 0};
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c >= nb) break;
+        cx<double> v = x[c];
+#pragma unroll
+        for (int d = 0; d < c; ++d) {
+          const cx<double> u = cmulcj_d(x[d], A[(kb + c) + (size_t)(kb + d) * lda]);
+          v.x -= u.x;
+          v.y -= u.y;
+        }
+        const double inv = 1.0 / A[(kb + c) + (size_t)(kb + c) * lda].x;
+        x[c] = {v.x * inv, v.y * inv};
       }
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nb) A[i + (size_t)(kb + c) * lda] = x[c];
     }
-    prev_inv = 1.0 / sqrt(d);
+    __syncthreads();
+    // trailing lower triangle
+    for (int j = kb + nb + wave; j < n; j += nw)
+      for (int i = j + lane; i < n; i += 64) {
+        cx<double> acc = A[i + (size_t)j * lda];
+        for (int c = 0; c < nb; ++c) {
+          const cx<double> u =
+              cmulcj_d(A[i + (size_t)(kb + c) * lda], A[j + (size_t)(kb + c) * lda]);
+          acc.x -= u.x;
+          acc.y -= u.y;
+        }
+        A[i + (size_t)j * lda] = acc;
+      }
     __syncthreads();
   }
-  __syncthreads();
   const int fail_k = failed;
-  if (fail_k == 0 && t == 0) {
-    const cx<double> v = A[(n - 1) + (size_t)(n - 1) * lda];
-    A[(n - 1) + (size_t)(n - 1) * lda] = {sqrt(v.x), 0.0};
-  }
-  __syncthreads();
   if (t == 0) *info = fail_k;
   if (fail_k != 0) return;
   if (Lout) {
@@ -102,55 +139,248 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
       for (int i = lane; i < n; i += 64)
         Lout[i + (size_t)j * n] = (i >= j) ? A[i + (size_t)j * lda] : cx<double>{0.0, 0.0};
   }
-  // in-place inverse of the lower triangle
-  for (int k = 0; k < n; ++k) {
-    const double xkk = 1.0 / A[k + (size_t)k * lda].x;  // diagonal is real
-    for (int i = k + 1 + lane; i < n; i += 64) {
-      const cx<double> lik = A[i + (size_t)k * lda];
-      for (int j0 = wave; j0 < k; j0 += 4 * nw) {
-        cx<double> akj[4], v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = j0 + u * nw < k ? j0 + u * nw : j0;
-          akj[u] = A[k + (size_t)j * lda];
-          v[u] = A[i + (size_t)j * lda];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (j0 + u * nw >= k) continue;
-          v[u].x -= (lik.x * akj[u].x - lik.y * akj[u].y) * xkk;
-          v[u].y -= (lik.x * akj[u].y + lik.y * akj[u].x) * xkk;
-          A[i + (size_t)(j0 + u * nw) * lda] = v[u];
-        }
+  __syncthreads();  // Lout read A before the diagonal blocks are overwritten
+
+  // ---- inverse: diagonal blocks in place (one wave each)
+  const int nbk = (n + NB - 1) / NB;
+  for (int b = wave; b < nbk; b += nw) {
+    const int kb = b * NB, nb = n - kb < NB ? n - kb : NB;
+    for (int k = kb; k < kb + nb; ++k) {
+      const double xkk = 1.0 / A[k + (size_t)k * lda].x;
+      wave_sync();
+      const int mi = kb + nb - k - 1, mj = k - kb;
+      for (int e = lane; e < mi * mj; e += 64) {
+        const int i = k + 1 + e % mi, j = kb + e / mi;
+        const cx<double> u = cmul_d(A[i + (size_t)k * lda], A[k + (size_t)j * lda]);
+        cx<double> v = A[i + (size_t)j * lda];
+        A[i + (size_t)j * lda] = {v.x - u.x * xkk, v.y - u.y * xkk};
       }
+      wave_sync();
+      for (int e = lane; e < mi; e += 64) {
+        const cx<double> v = A[(k + 1 + e) + (size_t)k * lda];
+        A[(k + 1 + e) + (size_t)k * lda] = {-v.x * xkk, -v.y * xkk};
+      }
+      for (int e = lane; e < mj; e += 64) {
+        const cx<double> v = A[k + (size_t)(kb + e) * lda];
+        A[k + (size_t)(kb + e) * lda] = {v.x * xkk, v.y * xkk};
+      }
+      if (lane == 0) A[k + (size_t)k * lda] = {xkk, 0.0};
+      wave_sync();
     }
-    __syncthreads();
-    for (int i = k + 1 + t; i < n; i += nt) {
-      const cx<double> v = A[i + (size_t)k * lda];
-      A[i + (size_t)k * lda] = {-v.x * xkk, -v.y * xkk};
-    }
-    for (int j = t; j < k; j += nt) {
-      const cx<double> v = A[k + (size_t)j * lda];
-      A[k + (size_t)j * lda] = {v.x * xkk, v.y * xkk};
-    }
-    if (t == 0) A[k + (size_t)k * lda] = {xkk, 0.0};
-    __syncthreads();
   }
-  // C = X^H (upper triangular)
+  __syncthreads();
+  // C = X^H: diagonal blocks now, zero strict lower part; the rest per block
+  // row.  Finished off-diagonal blocks of X are also kept, conjugated, in the
+  // unused strict upper triangle of A: X[k][j] sits at A[j + k lda] (j < k).
   for (int b = wave; b < n; b += nw)
     for (int a = lane; a < n; a += 64) {
-      const cx<double> x = (b >= a) ? A[b + (size_t)a * lda] : cx<double>{0.0, 0.0};
-      C[a + (size_t)b * n] = {x.x, -x.y};
+      if (b < a) {
+        C[a + (size_t)b * n] = {0.0, 0.0};
+      } else if (a / NB == b / NB) {
+        const cx<double> x = A[b + (size_t)a * lda];
+        C[a + (size_t)b * n] = {x.x, -x.y};
+      }
     }
+  for (int ib = 1; ib < nbk; ++ib) {
+    const int ri = ib * NB, ni = n - ri < NB ? n - ri : NB;
+    // T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]
+    for (int col = wave; col < ri; col += nw)
+      for (int r = lane; r < ni; r += 64) {
+        const int cb_end = (col / NB + 1) * NB;  // X[k][col] for k < cb_end: diagonal block
+        cx<double> acc = {0.0, 0.0};
+        for (int k = col; k < cb_end; ++k) {
+          const cx<double> u = cmul_d(A[(ri + r) + (size_t)k * lda], A[k + (size_t)col * lda]);
+          acc.x += u.x;
+          acc.y += u.y;
+        }
+#pragma unroll 4
+        for (int k = cb_end; k < ri; ++k) {
+          const cx<double> u =
+              cmulcj_d(A[(ri + r) + (size_t)k * lda], A[col + (size_t)k * lda]);
+          acc.x += u.x;
+          acc.y += u.y;
+        }
+        T[r + (size_t)col * NB] = acc;
+      }
+    __syncthreads();
+    // X[ri + r][col] = -sum_{q <= r} X_ii[r][q] T[q][col]
+    for (int col = wave; col < ri; col += nw)
+      for (int r = lane; r < ni; r += 64) {
+        cx<double> acc = {0.0, 0.0};
+        for (int q = 0; q <= r; ++q) {
+          const cx<double> u = cmul_d(A[(ri + r) + (size_t)(ri + q) * lda], T[q + (size_t)col * NB]);
+          acc.x += u.x;
+          acc.y += u.y;
+        }
+        const cx<double> xc = {-acc.x, acc.y};  // conj(X[ri + r][col])
+        A[col + (size_t)(ri + r) * lda] = xc;
+        C[col + (size_t)(ri + r) * n] = xc;
+      }
+    __syncthreads();
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_chol_inv_lds(const cx<double>* __restrict__ M, int n,
-                                                      double s, cx<double>* __restrict__ Lout,
-                                                      cx<double>* __restrict__ C,
-                                                      int* __restrict__ info,
-                                                      const int* __restrict__ prior) {
-  __shared__ cx<double> A[kCholLdsMax * (kCholLdsMax + 1)];
-  chol_inv_body(M, n, s, A, n + 1, Lout, C, info, prior);
+// ---------------------------------------------------------------------------
+// Fused factorisation for n <= kCholRegMax, one workgroup, matrix entries in
+// registers.  Every thread owns up to kCholSlots entries of the lower triangle
+// of A (the Cholesky side) and up to kCholSlots strictly-lower entries of
+// B (the inverse side) for the whole kernel; one barrier per column k.
+//   Cholesky  right-looking on the unscaled Schur complement:
+//             a_ij -= a_ik conj(a_jk) / a_kk  for i >= j > k,
+//             L_ik = a_ik / sqrt(a_kk).
+//   inverse   X = L^{-1} row by row in the same sweep: X_kj = B_kj / L_kk with
+//             B_kj = delta_kj - sum_{m<k} L_km X_mj, accumulated right-looking
+//             (B_ij -= L_ik X_kj for i > k >= j).
+// Column k of the Schur complement and row k of B become final during step
+// k - 1; their owners publish them to LDS (two buffers, alternating with the
+// parity of k), and after the barrier every thread reads what it needs for
+// step k.  A slot reads its LDS operands only while active (the LDS traffic of
+// reading every slot at every step would dominate), but the reads of all
+// slots are issued before the first is used.  The Cholesky entries are
+// numbered by column from the last one backwards, so the entries still active
+// at step k form a prefix and fill whole waves; within a wave the column
+// index is mostly uniform and its reads are broadcasts.
+constexpr int kCholRegMax = 88;
+constexpr int kCholSlots = 4;  // ceil(88 * 89 / 2 / 1024)
+
+__device__ __forceinline__ void tri_index_desc(int e, int n, int* i, int* j) {
+  // e-th entry of the lower triangle (incl. diagonal), columns n-1, n-2, ...
+  int jj = n - 1, len = 1;
+  while (e >= len) {
+    e -= len;
+    --jj;
+    ++len;
+  }
+  *j = jj;
+  *i = jj + e;
+}
+
+__device__ __forceinline__ void tri_index_strict(int e, int n, int* i, int* j) {
+  // e-th entry of the strict lower triangle, columns 0, 1, ...
+  int jj = 0, len = n - 1;
+  while (e >= len) {
+    e -= len;
+    ++jj;
+    --len;
+  }
+  *j = jj;
+  *i = jj + 1 + e;
+}
+
+// 1/sqrt(d) from the hardware estimate, refined by three Newton-Raphson steps
+// y <- y (3/2 - d y^2 / 2); then 1/d = y^2 and sqrt(d) = d y.
+__device__ __forceinline__ void pivot_terms(double d, double* invr, double* invd, double* r) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+  }
+  *invr = y;
+  *invd = y * y;
+  *r = d * y;
+}
+
+__global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restrict__ M, int n,
+                                                       double s, cx<double>* __restrict__ Lout,
+                                                       cx<double>* __restrict__ C,
+                                                       int* __restrict__ info,
+                                                       const int* __restrict__ prior) {
+  __shared__ cx<double> colA[2][kCholRegMax];
+  __shared__ cx<double> rowB[2][kCholRegMax];
+  const int t = threadIdx.x, nt = blockDim.x;
+  if (prior && *prior != 0) {
+    if (t == 0) *info = *prior;
+    return;
+  }
+  const int tot_a = n * (n + 1) / 2, tot_b = n * (n - 1) / 2;
+  // owned entries; an unused slot gets indices that no step activates
+  int ai[kCholSlots], aj[kCholSlots], bi[kCholSlots], bj[kCholSlots];
+  cx<double> a[kCholSlots], bv[kCholSlots];
+#pragma unroll
+  for (int q = 0; q < kCholSlots; ++q) {
+    const int e = t + q * nt;
+    ai[q] = aj[q] = 0;  // column 0 is never updated
+    bi[q] = 0;          // i > k never holds
+    bj[q] = n;
+    if (e < tot_a) tri_index_desc(e, n, &ai[q], &aj[q]);
+    if (e < tot_b) tri_index_strict(e, n, &bi[q], &bj[q]);
+  }
+  // A = s (M + M^H) / 2 on the owned entries; all loads issued together
+  cx<double> m1[kCholSlots], m2[kCholSlots];
+#pragma unroll
+  for (int q = 0; q < kCholSlots; ++q) {
+    m1[q] = m2[q] = {0.0, 0.0};
+    if (t + q * nt < tot_a) {
+      m1[q] = M[ai[q] + (size_t)aj[q] * n];
+      m2[q] = M[aj[q] + (size_t)ai[q] * n];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCholSlots; ++q) {
+    a[q] = ai[q] == aj[q] ? cx<double>{s * m1[q].x, 0.0}
+                          : cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.5 * s * (m1[q].y - m2[q].y)};
+    bv[q] = {0.0, 0.0};
+    if (t + q * nt < tot_a && aj[q] == 0) colA[0][ai[q]] = a[q];
+  }
+  __syncthreads();
+  int fail_k = 0;
+  for (int k = 0; k < n; ++k) {
+    const int p = k & 1;
+    const double d = colA[p][k].x;
+    // operands of the active slots, all issued before the first use
+    cx<double> ci[kCholSlots], cj[kCholSlots], li[kCholSlots], xk[kCholSlots];
+#pragma unroll
+    for (int q = 0; q < kCholSlots; ++q) {
+      if (aj[q] > k) {  // i >= j > k
+        ci[q] = colA[p][ai[q]];
+        cj[q] = colA[p][aj[q]];
+      }
+      if (bj[q] <= k && k < bi[q]) {  // i > k >= j
+        li[q] = colA[p][bi[q]];
+        xk[q] = rowB[p][bj[q]];
+      }
+    }
+    cx<double> oc = {0.0, 0.0};
+    if (t < n) oc = t > k ? colA[p][t] : rowB[p][t];
+    if (!(d > 0.0) || !isfinite(d)) {  // the same value in every thread
+      fail_k = k + 1;
+      break;
+    }
+    double invr, invd, r;
+    pivot_terms(d, &invr, &invd, &r);
+    // column k of L and of C = X^H (row k of X), zeros elsewhere
+    if (t < n) {
+      if (Lout)
+        Lout[t + (size_t)k * n] = t < k    ? cx<double>{0.0, 0.0}
+                                  : t == k ? cx<double>{r, 0.0}
+                                           : cx<double>{oc.x * invr, oc.y * invr};
+      C[t + (size_t)k * n] = t > k    ? cx<double>{0.0, 0.0}
+                             : t == k ? cx<double>{invr, 0.0}
+                                      : cx<double>{oc.x * invr, -oc.y * invr};
+    }
+#pragma unroll
+    for (int q = 0; q < kCholSlots; ++q)
+      if (aj[q] > k) {
+        const cx<double> u = cmulcj_d(ci[q], cj[q]);
+        a[q].x -= u.x * invd;
+        a[q].y -= u.y * invd;
+        if (aj[q] == k + 1) colA[p ^ 1][ai[q]] = a[q];
+      }
+    // inverse side: L_ik X_kj = (a_ik / r) (B_kj / r), B_kk = 1
+#pragma unroll
+    for (int q = 0; q < kCholSlots; ++q)
+      if (bj[q] <= k && k < bi[q]) {
+        const cx<double> xr = bj[q] == k ? cx<double>{1.0, 0.0} : xk[q];
+        const cx<double> u = cmul_d(li[q], xr);
+        bv[q].x -= u.x * invd;
+        bv[q].y -= u.y * invd;
+        if (bi[q] == k + 1) rowB[p ^ 1][bj[q]] = bv[q];
+      }
+    __syncthreads();
+  }
+  if (t == 0) *info = fail_k;
 }
 
 __global__ __launch_bounds__(1024) void k_chol_inv_global(const cx<double>* __restrict__ M, int n,
@@ -159,7 +389,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv_global(const cx<double>* __re
                                                           cx<double>* __restrict__ C,
                                                           int* __restrict__ info,
                                                           const int* __restrict__ prior) {
-  chol_inv_body(M, n, s, A, n, Lout, C, info, prior);
+  chol_inv_body(M, n, s, A, n, A + (size_t)n * n, Lout, C, info, prior);
 }
 
 __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A, long count,
@@ -180,9 +410,13 @@ __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A
 
 ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
                     cx<double>* C, cx<double>* scratch, int* info_dev, const int* prior) {
-  if (n <= kCholLdsMax)
-    return launch(c, "chol_inv_lds", k_chol_inv_lds, dim3(1), dim3(1024), 0, M, n, s, Lout, C,
+  if (n <= kCholRegMax) {
+    // enough threads for kCholSlots entries each, whole waves
+    const int need = (n * (n + 1) / 2 + kCholSlots - 1) / kCholSlots;
+    const int threads = need < 64 ? 64 : (need + 63) / 64 * 64;
+    return launch(c, "chol_inv_reg", k_chol_inv_reg, dim3(1), dim3(threads), 0, M, n, s, Lout, C,
                   info_dev, prior);
+  }
   return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
                 Lout, C, info_dev, prior);
 }

@@ -88,27 +88,56 @@ __device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0
   }
 }
 
-// One-thread-per-line variants of the slab and plane passes (a workgroup of N
-// threads, each owning a whole row or column in registers).
-
-// Forward slab pass: one workgroup of N threads per (x0, pair).
+// One-thread-per-line variants of the slab and plane passes: each thread owns
+// a whole row or column in registers.  A workgroup takes P slabs (planes) of
+// N lines each, P chosen so that P N fills whole waves within an LDS budget
+// (N = 48 planes: four in three full waves instead of one wave of 48 lanes).
+// The slab pass gets the smaller budget: it issues two loads per value and
+// measured slower at N = 48 with four slabs (fewer workgroups per CU).
 template <int N, typename T>
-__global__ __launch_bounds__(N) void k_pair_fwd_slab_t1(const cx<T>* __restrict__ phi, long ldphi,
-                                                     const cx<T>* __restrict__ psi, long ldpsi,
-                                                     cx<T>* __restrict__ buf, int mode, int i0,
-                                                     int A, int j0, long p0, int npairs) {
+constexpr int t1_group(long lds_budget) {
+  int best = 1;
+  double best_use = 0.0;
+  for (int P = 1; P <= 16; ++P) {
+    const long lds = (long)P * N * (N + 1) * (long)sizeof(cx<T>);
+    if (P * N > 1024 || lds > lds_budget) break;
+    const int waves = (P * N + 63) / 64;
+    const double use = (double)(P * N) / (64.0 * waves);
+    if (use > best_use + 1e-9) {
+      best_use = use;
+      best = P;
+    }
+  }
+  return best;
+}
+
+// Forward slab pass: one group of N threads per (x0, pair).
+template <int N, typename T, int P>
+__global__ __launch_bounds__(N * P) void k_pair_fwd_slab_t1(const cx<T>* __restrict__ phi, long ldphi,
+                                                         const cx<T>* __restrict__ psi, long ldpsi,
+                                                         cx<T>* __restrict__ buf, int mode, int i0,
+                                                         int A, int j0, long p0, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
-  __shared__ cx<T> s[N * LD];
-  const long lid = xcd_logical(blockIdx.x, gridDim.x);
-  if (lid >= (long)N * npairs) return;
+  __shared__ cx<T> s_all[P * N * LD];
+  const long total = (long)N * npairs;
+  const long lid0 = xcd_logical(blockIdx.x, gridDim.x) * P;
+  if (lid0 >= total) return;  // the whole workgroup
+  // group q of the workgroup (compile-time 0 when P = 1, keeping the LDS
+  // addresses constant offsets)
+  const int q = P == 1 ? 0 : (int)threadIdx.x / N;
+  const int t = P == 1 ? (int)threadIdx.x : (int)threadIdx.x - q * N;
+  cx<T>* s = s_all + q * N * LD;
+  // a group past the end (only in the last workgroup) redoes the last unit
+  // and does not store
+  const bool live = P == 1 || lid0 + q < total;
+  const long lid = live ? lid0 + q : total - 1;
   const int x0 = (int)(lid / npairs);
   const int p = (int)(lid - (long)x0 * npairs);
   int i, j;
   pair_of(mode, i0, A, j0, p0, p, &i, &j);
   const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
   const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
-  const int t = threadIdx.x;
   {
     // issue every load of the slab before the first use
     cx<T> va[N], vb[N];
@@ -122,34 +151,44 @@ __global__ __launch_bounds__(N) void k_pair_fwd_slab_t1(const cx<T>* __restrict_
   __syncthreads();
   cx<T> v[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
+  for (int k = 0; k < N; ++k) v[k] = s[t * LD + k];
   fft_line<N, -1, T>(v);
 #pragma unroll
-  for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
+  for (int k = 0; k < N; ++k) s[t * LD + k] = v[k];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = s[q * LD + t];
+  for (int k = 0; k < N; ++k) v[k] = s[k * LD + t];
   fft_line<N, -1, T>(v);
+  if (!live) return;
   cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
 #pragma unroll
-  for (int q = 0; q < N; ++q) out[q * N + t] = v[q];
+  for (int k = 0; k < N; ++k) out[k * N + t] = v[k];
 }
 
-// Plane pass: one workgroup of N threads per (k1 plane, pair).  The plane
+// Plane pass: one group of N threads per (k1 plane, pair).  The plane
 // buf[k0][k1][.] (N rows of N contiguous values, rows N^2 apart) goes through
 // LDS: forward FFT along axis 0, multiply by K', inverse FFT along axis 0, then
 // inverse FFT along axis 2.  Loads and stores are contiguous N-wide rows.
-template <int N, typename T>
-__global__ __launch_bounds__(N) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
-                                                    const T* __restrict__ Kt, int npairs) {
+template <int N, typename T, int P>
+__global__ __launch_bounds__(N * P) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
+                                                        const T* __restrict__ Kt, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
-  __shared__ cx<T> s[N * LD];
-  const long lid = xcd_logical(blockIdx.x, gridDim.x);
-  if (lid >= (long)N * npairs) return;
+  __shared__ cx<T> s_all[P * N * LD];
+  const long total = (long)N * npairs;
+  const long lid0 = xcd_logical(blockIdx.x, gridDim.x) * P;
+  if (lid0 >= total) return;  // the whole workgroup
+  // group q of the workgroup (compile-time 0 when P = 1, keeping the LDS
+  // addresses constant offsets)
+  const int q = P == 1 ? 0 : (int)threadIdx.x / N;
+  const int t = P == 1 ? (int)threadIdx.x : (int)threadIdx.x - q * N;
+  cx<T>* s = s_all + q * N * LD;
+  // a group past the end (only in the last workgroup) redoes the last unit
+  // and does not store
+  const bool live = P == 1 || lid0 + q < total;
+  const long lid = live ? lid0 + q : total - 1;
   const int k1 = (int)(lid / npairs);
   const int p = (int)(lid - (long)k1 * npairs);
-  const int t = threadIdx.x;
   cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
   cx<T> v[N];
   // axis 0 (column t of the plane, k2 = t): forward, kernel, inverse.  The
@@ -170,11 +209,12 @@ __global__ __launch_bounds__(N) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
   __syncthreads();
   // axis 2 (row t of the plane, x0 = t): inverse
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = s[t * LD + q];
+  for (int k = 0; k < N; ++k) v[k] = s[t * LD + k];
   fft_line<N, +1, T>(v);
 #pragma unroll
-  for (int q = 0; q < N; ++q) s[t * LD + q] = v[q];
+  for (int k = 0; k < N; ++k) s[t * LD + k] = v[k];
   __syncthreads();
+  if (!live) return;
 #pragma unroll
   for (int r = 0; r < N; ++r) plane[(size_t)r * NN + t] = s[r * LD + t];
 }
@@ -471,8 +511,10 @@ ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx
   if (quad)
     return launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, grid, dim3(4 * N), 0, phi, ldphi, psi,
                   ldpsi, buf, mode, i0, A, j0, p0, np);
-  return launch(c, "pair_fwd_slab", k_pair_fwd_slab_t1<N, T>, grid, dim3(N), 0, phi, ldphi, psi,
-                ldpsi, buf, mode, i0, A, j0, p0, np);
+  constexpr int P = t1_group<N, T>(40 * 1024);
+  return launch(c, "pair_fwd_slab", k_pair_fwd_slab_t1<N, T, P>,
+                dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, phi, ldphi, psi, ldpsi,
+                buf, mode, i0, A, j0, p0, np);
 }
 
 template <int N, typename T>
@@ -480,7 +522,9 @@ ace_status plane(ace_ctx c, bool quad, cx<T>* buf, const T* Kt, int np) {
   const dim3 grid(xcd_pad((long)N * np));
   if (quad)
     return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, Kt, np);
-  return launch(c, "plane_kernel", k_plane_kernel_t1<N, T>, grid, dim3(N), 0, buf, Kt, np);
+  constexpr int P = t1_group<N, T>(80 * 1024);
+  return launch(c, "plane_kernel", k_plane_kernel_t1<N, T, P>,
+                dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, buf, Kt, np);
 }
 
 template <int N, typename T>

@@ -61,35 +61,91 @@ __device__ __forceinline__ float bf16_to_float(unsigned short h) {
 __device__ __forceinline__ __bf16 as_bf16(unsigned short h) {
   return __builtin_bit_cast(__bf16, h);
 }
+// (v1, -v0, v3, -v2, ...) of eight BF16 values, on the 32-bit words.
+__device__ __forceinline__ v8bf partner_neg(v8bf v) {
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  v4u w = __builtin_bit_cast(v4u, v);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = ((w[i] >> 16) | (w[i] << 16)) ^ 0x80000000u;
+  return __builtin_bit_cast(v8bf, w);
+}
 
 // ---------------------------------------------------------------------------
-// Reduction product, FP32 or FP64 MFMA.  A wave owns a 32 x 32 complex tile
-// (2 x 2 MFMA blocks); the 4 waves of a workgroup take interleaved 8-point K
-// steps of the same tile and are summed through LDS; one partial per
-// workgroup (split K over blockIdx.z), combined later in FP64.
+// Reduction products.  A workgroup of TA x TB waves (blockDim = (64 TA, TB))
+// covers up to 32 TA x 32 TB outputs, one wave per 32 x 32 complex tile (2 x 2
+// MFMA blocks), every wave walking the same K chunk: rows shared by the waves
+// of a workgroup come from HBM once and are served to the others by the CU's
+// caches.  K is split over blockIdx.z; each wave writes its FP32 (or FP64)
+// accumulators unchanged as one partial, and the partials are summed in FP64
+// in a fixed order afterwards.  16 x 16 blocks that lie wholly outside the
+// output are skipped (a wave-uniform test), so an 80 x 80 product costs 25
+// blocks of MFMA work, not 36.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cn_mfma(const cx<T>* __restrict__ A, long lda, int na,
-                                                 const cx<T>* __restrict__ B, long ldb, int nb,
-                                                 long K, long kchunk,
-                                                 cx<double>* __restrict__ partial) {
-  typedef typename Acc4<T>::type acc_t;
-  __shared__ double red[4][2][2][2][4][64];  // wave, alpha, beta, re/im, v, lane
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r16 = lane & 15, kq = lane >> 4;
-  const int a0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
-  const long kbeg = (long)blockIdx.z * kchunk;
-  const long kend = kbeg + kchunk < K ? kbeg + kchunk : K;
+struct TileRows {
   const cx<T>* pa[2];
   const cx<T>* pb[2];
-  bool va[2], vb[2];
+  bool va[2], vb[2];  // this lane's row inside the output
+  bool ba[2], bb[2];  // any row of the 16-block inside (wave-uniform)
+  int a0, b0;
+};
+
+// Tile of wave w of the workgroup.  The workgroup's tiles are taken in the
+// order: tiles wholly inside the output first, then the cut ones, each group
+// row by row; waves go to SIMDs round robin, so the heavy tiles spread over
+// all four SIMDs instead of piling on one.
+template <typename T>
+__device__ __forceinline__ TileRows<T> tile_rows(const cx<T>* A, long lda, int na, const cx<T>* B,
+                                                 long ldb, int nb, int r16) {
+  TileRows<T> t;
+  const int ta = blockDim.x >> 6, tb = blockDim.y;
+  const int w = (threadIdx.y * blockDim.x + threadIdx.x) >> 6;
+  const int gx0 = blockIdx.x * ta, gy0 = blockIdx.y * tb;
+  int n_full_a = (na / 32) - gx0, n_full_b = (nb / 32) - gy0;
+  n_full_a = n_full_a < 0 ? 0 : n_full_a > ta ? ta : n_full_a;
+  n_full_b = n_full_b < 0 ? 0 : n_full_b > tb ? tb : n_full_b;
+  int tx, ty;
+  if (w < n_full_a * n_full_b) {
+    tx = w % n_full_a;
+    ty = w / n_full_a;
+  } else {
+    int m = w - n_full_a * n_full_b;  // m-th cut tile, row by row
+    tx = 0;
+    ty = 0;
+    for (int q = 0; q < ta * tb; ++q) {
+      const int qx = q % ta, qy = q / ta;
+      if (qx < n_full_a && qy < n_full_b) continue;
+      if (m-- == 0) {
+        tx = qx;
+        ty = qy;
+        break;
+      }
+    }
+  }
+  t.a0 = (gx0 + tx) * 32;
+  t.b0 = (gy0 + ty) * 32;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int ra = a0 + 16 * h + r16, rb = b0 + 16 * h + r16;
-    va[h] = ra < na;
-    vb[h] = rb < nb;
-    pa[h] = A + (size_t)(va[h] ? ra : 0) * lda;
-    pb[h] = B + (size_t)(vb[h] ? rb : 0) * ldb;
+    const int ra = t.a0 + 16 * h + r16, rb = t.b0 + 16 * h + r16;
+    t.va[h] = ra < na;
+    t.vb[h] = rb < nb;
+    t.ba[h] = t.a0 + 16 * h < na;
+    t.bb[h] = t.b0 + 16 * h < nb;
+    t.pa[h] = A + (size_t)(t.va[h] ? ra : 0) * lda;
+    t.pb[h] = B + (size_t)(t.vb[h] ? rb : 0) * ldb;
   }
+  return t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
+    const cx<T>* __restrict__ A, long lda, int na, const cx<T>* __restrict__ B, long ldb, int nb,
+    long K, long kchunk, cx<T>* __restrict__ partial) {
+  typedef typename Acc4<T>::type acc_t;
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const TileRows<T> t = tile_rows<T>(A, lda, na, B, ldb, nb, r16);
+  if (!t.ba[0] || !t.bb[0]) return;  // whole wave outside the output
+  const long kbeg = (long)blockIdx.z * kchunk;
+  const long kend = kbeg + kchunk < K ? kbeg + kchunk : K;
   acc_t cre[2][2], cim[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -98,41 +154,47 @@ __global__ __launch_bounds__(256) void k_cn_mfma(const cx<T>* __restrict__ A, lo
       cre[x][y] = acc_t{0, 0, 0, 0};
       cim[x][y] = acc_t{0, 0, 0, 0};
     }
-  constexpr int U = 4;  // steps per iteration (loads issued together)
-  for (long k0 = kbeg + 8 * wave; k0 < kend; k0 += 32 * U) {
-    T a[U][2][4], b[U][2][4];
+  // Rolling pipeline over 8-point steps: the loads of step i + R - 1 are
+  // issued before the MFMAs of step i, so R - 1 steps are always in flight.
+  constexpr int R = sizeof(T) == 8 ? 2 : 4;
+  T a[R][2][4], b[R][2][4];
+  auto load = [&](T (&ar)[2][4], T (&br)[2][4], long k) {
+    const bool kin = k < kend;  // K and kchunk are even: k + 1 is in range too
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long k = k0 + 32 * u + 2 * kq;
-      const bool kin = k < kend;  // N_g and kchunk are even: k + 1 is in range too
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        cx<T> x0 = {T(0), T(0)}, x1 = {T(0), T(0)}, y0 = {T(0), T(0)}, y1 = {T(0), T(0)};
-        if (kin && va[h]) {
-          x0 = pa[h][k];
-          x1 = pa[h][k + 1];
-        }
-        if (kin && vb[h]) {
-          y0 = pb[h][k];
-          y1 = pb[h][k + 1];
-        }
-        a[u][h][0] = x0.x; a[u][h][1] = x0.y; a[u][h][2] = x1.x; a[u][h][3] = x1.y;
-        b[u][h][0] = y0.x; b[u][h][1] = y0.y; b[u][h][2] = y1.x; b[u][h][3] = y1.y;
+    for (int h = 0; h < 2; ++h) {
+      cx<T> x0 = {T(0), T(0)}, x1 = {T(0), T(0)}, y0 = {T(0), T(0)}, y1 = {T(0), T(0)};
+      if (kin && t.va[h]) {
+        x0 = t.pa[h][k];
+        x1 = t.pa[h][k + 1];
       }
+      if (kin && t.vb[h]) {
+        y0 = t.pb[h][k];
+        y1 = t.pb[h][k + 1];
+      }
+      ar[h][0] = x0.x; ar[h][1] = x0.y; ar[h][2] = x1.x; ar[h][3] = x1.y;
+      br[h][0] = y0.x; br[h][1] = y0.y; br[h][2] = y1.x; br[h][3] = y1.y;
     }
+  };
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+  for (int j = 0; j < R - 1; ++j) load(a[j], b[j], kbeg + 8 * j + 2 * kq);
+  for (long k0 = kbeg; k0 < kend; k0 += 8 * R) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+    for (int j = 0; j < R; ++j) {
+      const int nx = (j + R - 1) % R;
+      load(a[nx], b[nx], k0 + 8 * (j + R - 1) + 2 * kq);
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            const T bs = b[u][y][s];
-            const T bpp = (s & 1) ? -b[u][y][s ^ 1] : b[u][y][s ^ 1];
-            cre[x][y] = mfma4(a[u][x][s], bs, cre[x][y]);
-            cim[x][y] = mfma4(a[u][x][s], bpp, cim[x][y]);
+        for (int y = 0; y < 2; ++y) {
+          if (!t.ba[x] || !t.bb[y]) continue;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const T bpp = (s & 1) ? -b[j][y][s ^ 1] : b[j][y][s ^ 1];
+            cre[x][y] = mfma4(a[j][x][s], b[j][y][s], cre[x][y]);
+            cim[x][y] = mfma4(a[j][x][s], bpp, cim[x][y]);
           }
+        }
+    }
   }
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -140,24 +202,11 @@ __global__ __launch_bounds__(256) void k_cn_mfma(const cx<T>* __restrict__ A, lo
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        red[wave][x][y][0][v][lane] = (double)cre[x][y][v];
-        red[wave][x][y][1][v][lane] = (double)cim[x][y][v];
+        const int ra = t.a0 + 16 * x + mfma_row<T>(lane, v);
+        const int rb = t.b0 + 16 * y + r16;
+        if (ra < na && rb < nb)
+          partial[((size_t)blockIdx.z * nb + rb) * na + ra] = {cre[x][y][v], cim[x][y][v]};
       }
-  __syncthreads();
-  // 256 threads write the 32 x 32 tile: thread -> (x, y, v, lane) over 2*2*4*64/4
-  for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += 256) {
-    const int l = e & 63, v = (e >> 6) & 3, y = (e >> 8) & 1, x = (e >> 9) & 1;
-    double sr = 0.0, si = 0.0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      sr += red[w][x][y][0][v][l];
-      si += red[w][x][y][1][v][l];
-    }
-    const int ra = a0 + 16 * x + mfma_row<T>(l, v);
-    const int rb = b0 + 16 * y + (l & 15);
-    if (ra < na && rb < nb)
-      partial[((size_t)blockIdx.z * nb + rb) * na + ra] = {sr, si};
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -165,27 +214,16 @@ __global__ __launch_bounds__(256) void k_cn_mfma(const cx<T>* __restrict__ A, lo
 // with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on the
 // 16x16x32 BF16 MFMA with FP32 accumulation (the lo*lo term, ~2^-16 relative,
 // is dropped).  A lane's 8 K slots are 4 consecutive complex grid values.
-__global__ __launch_bounds__(256) void k_cn_mfma_bf16x3(const cx<float>* __restrict__ A, long lda,
-                                                        int na, const cx<float>* __restrict__ B,
-                                                        long ldb, int nb, long K, long kchunk,
-                                                        cx<double>* __restrict__ partial) {
-  __shared__ double red[4][2][2][2][4][64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r16 = lane & 15, kq = lane >> 4;
-  const int a0 = blockIdx.x * 32, b0 = blockIdx.y * 32;
+// Same workgroup shape and partials as k_cn_mfma.
+__global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restrict__ A, long lda,
+                                                         int na, const cx<float>* __restrict__ B,
+                                                         long ldb, int nb, long K, long kchunk,
+                                                         cx<float>* __restrict__ partial) {
+  const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+  const TileRows<float> t = tile_rows<float>(A, lda, na, B, ldb, nb, r16);
+  if (!t.ba[0] || !t.bb[0]) return;
   const long kbeg = (long)blockIdx.z * kchunk;
   const long kend = kbeg + kchunk < K ? kbeg + kchunk : K;
-  const cx<float>* pa[2];
-  const cx<float>* pb[2];
-  bool va[2], vb[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int ra = a0 + 16 * h + r16, rb = b0 + 16 * h + r16;
-    va[h] = ra < na;
-    vb[h] = rb < nb;
-    pa[h] = A + (size_t)(va[h] ? ra : 0) * lda;
-    pb[h] = B + (size_t)(vb[h] ? rb : 0) * ldb;
-  }
   v4f cre[2][2], cim[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -194,58 +232,56 @@ __global__ __launch_bounds__(256) void k_cn_mfma_bf16x3(const cx<float>* __restr
       cre[x][y] = v4f{0, 0, 0, 0};
       cim[x][y] = v4f{0, 0, 0, 0};
     }
-  constexpr int U = 2;
-  for (long k0 = kbeg + 16 * wave; k0 < kend; k0 += 64 * U) {
-    float a[U][2][8], b[U][2][8];
+  // Two-slot pipeline over 16-point steps: the raw loads of step i + 1 are
+  // issued before step i is split into BF16 halves and multiplied.
+  float a[2][2][8], b[2][2][8];
+  auto load = [&](float (&ar)[2][8], float (&br)[2][8], long k) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const long k = k0 + 64 * u + 4 * kq;
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          cx<float> x = {0.f, 0.f}, y = {0.f, 0.f};
-          if (k + q < kend && va[h]) x = pa[h][k + q];
-          if (k + q < kend && vb[h]) y = pb[h][k + q];
-          a[u][h][2 * q] = x.x; a[u][h][2 * q + 1] = x.y;
-          b[u][h][2 * q] = y.x; b[u][h][2 * q + 1] = y.y;
-        }
+      for (int q = 0; q < 4; ++q) {
+        cx<float> x = {0.f, 0.f}, y = {0.f, 0.f};
+        if (k + q < kend && t.va[h]) x = t.pa[h][k + q];
+        if (k + q < kend && t.vb[h]) y = t.pb[h][k + q];
+        ar[h][2 * q] = x.x; ar[h][2 * q + 1] = x.y;
+        br[h][2 * q] = y.x; br[h][2 * q + 1] = y.y;
       }
     }
+  };
+  load(a[0], b[0], kbeg + 4 * kq);
+  for (long k0 = kbeg; k0 < kend; k0 += 32) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      v8bf ahi[2], alo[2], bhi[2], blo[2], phi_[2], plo[2];
+    for (int j = 0; j < 2; ++j) {
+      load(a[j ^ 1], b[j ^ 1], k0 + 16 * (j + 1) + 4 * kq);
+      v8bf ahi[2], alo[2], bhi[2], blo[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const unsigned short ah = bf16_bits(a[u][h][s]);
-          const unsigned short al = bf16_bits(a[u][h][s] - bf16_to_float(ah));
-          const unsigned short bh = bf16_bits(b[u][h][s]);
-          const unsigned short bl = bf16_bits(b[u][h][s] - bf16_to_float(bh));
+          const unsigned short ah = bf16_bits(a[j][h][s]);
+          const unsigned short bh = bf16_bits(b[j][h][s]);
           ahi[h][s] = as_bf16(ah);
-          alo[h][s] = as_bf16(al);
+          alo[h][s] = as_bf16(bf16_bits(a[j][h][s] - bf16_to_float(ah)));
           bhi[h][s] = as_bf16(bh);
-          blo[h][s] = as_bf16(bl);
-          // b'' = (im0, -re0, im1, -re1, ...): slot s takes the partner value,
-          // negated (sign bit flipped) in the odd slots
-          const int d = s ^ 1;
-          const unsigned short sign = (d & 1) ? 0x8000 : 0;
-          phi_[h][d] = as_bf16((unsigned short)(bh ^ sign));
-          plo[h][d] = as_bf16((unsigned short)(bl ^ sign));
+          blo[h][s] = as_bf16(bf16_bits(b[j][h][s] - bf16_to_float(bh)));
         }
       }
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        // b'' = (im0, -re0, im1, -re1, ...): swap the two halves of every
+        // 32-bit word and flip the sign of the upper one
+        const v8bf phi_ = partner_neg(bhi[y]), plo = partner_neg(blo[y]);
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
+        for (int x = 0; x < 2; ++x) {
+          if (!t.ba[x] || !t.bb[y]) continue;
           cre[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], bhi[y], cre[x][y], 0, 0, 0);
           cre[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], blo[y], cre[x][y], 0, 0, 0);
           cre[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[x], bhi[y], cre[x][y], 0, 0, 0);
-          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], phi_[y], cim[x][y], 0, 0, 0);
-          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], plo[y], cim[x][y], 0, 0, 0);
-          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[x], phi_[y], cim[x][y], 0, 0, 0);
+          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], phi_, cim[x][y], 0, 0, 0);
+          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[x], plo, cim[x][y], 0, 0, 0);
+          cim[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[x], phi_, cim[x][y], 0, 0, 0);
         }
+      }
     }
   }
 #pragma unroll
@@ -254,83 +290,84 @@ __global__ __launch_bounds__(256) void k_cn_mfma_bf16x3(const cx<float>* __restr
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        red[wave][x][y][0][v][lane] = (double)cre[x][y][v];
-        red[wave][x][y][1][v][lane] = (double)cim[x][y][v];
+        const int ra = t.a0 + 16 * x + mfma_row<float>(lane, v);
+        const int rb = t.b0 + 16 * y + r16;
+        if (ra < na && rb < nb)
+          partial[((size_t)blockIdx.z * nb + rb) * na + ra] = {cre[x][y][v], cim[x][y][v]};
       }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 2 * 2 * 4 * 64; e += 256) {
-    const int l = e & 63, v = (e >> 6) & 3, y = (e >> 8) & 1, x = (e >> 9) & 1;
-    double sr = 0.0, si = 0.0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      sr += red[w][x][y][0][v][l];
-      si += red[w][x][y][1][v][l];
-    }
-    const int ra = a0 + 16 * x + mfma_row<float>(l, v);
-    const int rb = b0 + 16 * y + (l & 15);
-    if (ra < na && rb < nb)
-      partial[((size_t)blockIdx.z * nb + rb) * na + ra] = {sr, si};
-  }
 }
 
-// C[a + b ldc] = alpha * sum_k partial[k][b][a]: 16 threads per element, each
-// summing every 16th partial, combined in a fixed-order tree (deterministic).
-__global__ __launch_bounds__(256) void k_reduce_partials2(const cx<double>* __restrict__ partial,
-                                                          int ks, int na, int nb, double alpha,
-                                                          cx<double>* __restrict__ C, int ldc) {
-  __shared__ double red[2][16][16];
-  const int g = threadIdx.x & 15, el = threadIdx.x >> 4;
-  const int idx = blockIdx.x * 16 + el;
+// C[a + b ldc] = alpha * sum_k partial[k][b][a] in FP64: a workgroup takes
+// 64 consecutive elements (one per lane, coalesced), its 16 waves sum every
+// 16th partial each and are combined in a fixed-order tree (deterministic).
+template <typename P>
+__global__ __launch_bounds__(1024) void k_reduce_partials2(const cx<P>* __restrict__ partial,
+                                                           int ks, int na, int nb, double alpha,
+                                                           cx<double>* __restrict__ C, int ldc) {
+  __shared__ double red[2][16][64];
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + el;
   double sr = 0.0, si = 0.0;
   if (idx < na * nb) {
     for (int k = g; k < ks; k += 16) {
-      const cx<double> v = partial[(size_t)k * na * nb + idx];
-      sr += v.x;
-      si += v.y;
+      const cx<P> v = partial[(size_t)k * na * nb + idx];
+      sr += (double)v.x;
+      si += (double)v.y;
     }
   }
-  red[0][el][g] = sr;
-  red[1][el][g] = si;
+  red[0][g][el] = sr;
+  red[1][g][el] = si;
   __syncthreads();
   for (int w = 8; w > 0; w >>= 1) {
     if (g < w) {
-      red[0][el][g] += red[0][el][g + w];
-      red[1][el][g] += red[1][el][g + w];
+      red[0][g][el] += red[0][g + w][el];
+      red[1][g][el] += red[1][g + w][el];
     }
     __syncthreads();
   }
   if (g == 0 && idx < na * nb) {
     const int a = idx % na, b = idx / na;
-    C[a + (size_t)b * ldc] = {alpha * red[0][el][0], alpha * red[1][el][0]};
+    C[a + (size_t)b * ldc] = {alpha * red[0][0][el], alpha * red[1][0][el]};
   }
 }
 
 // ---------------------------------------------------------------------------
-// Expansion product Y_b[r] = sum_a A_a[r] C[a + b ldc].  A workgroup of 4 waves
-// covers 128 grid rows (32 per wave, 2 MFMA row blocks) and 16 NBB columns;
-// C is staged in LDS 64 orbitals at a time in the accumulation type.
+// Expansion product Y_b[r] = sum_a A_a[r] C[a + b ldc].  A workgroup of 4
+// waves covers 4 x 16 XB grid rows (16 XB per wave: XB MFMA row blocks) and
+// 16 NBB columns; C is staged in LDS KC orbitals at a time in the
+// accumulation type.  With FP64 accumulation (64-cycle MFMAs, 8 registers per
+// 16 x 16 block) a wave keeps one row block and the chunk is 32 orbitals, so
+// that two or more waves fit on each SIMD to hide the grid-row loads.
+template <typename TAcc>
+struct NnShape {
+  static constexpr int XB = sizeof(TAcc) == 8 ? 1 : 2;
+  static constexpr int KC = sizeof(TAcc) == 8 ? 32 : 64;
+  static constexpr int ROWS = 64 * XB;  // grid rows per workgroup
+};
+
 template <typename TIn, typename TAcc, int NBB>
 __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, long lda, int na,
                                                  const cx<double>* __restrict__ C, int ldc, int nb,
                                                  cx<TIn>* __restrict__ Y, long ldy, long K) {
   typedef typename Acc4<TAcc>::type acc_t;
+  constexpr int XB = NnShape<TAcc>::XB, KC = NnShape<TAcc>::KC;
   constexpr int NBC = 16 * NBB;
-  __shared__ TAcc cs_re[64][NBC];
-  __shared__ TAcc cs_im[64][NBC];
+  __shared__ TAcc cs_re[KC][NBC];
+  __shared__ TAcc cs_im[KC][NBC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
-  const long rt0 = (long)blockIdx.x * 128 + 32 * wave;
+  const long rt0 = (long)blockIdx.x * NnShape<TAcc>::ROWS + 16 * XB * wave;
   const int b0 = blockIdx.y * NBC;
-  acc_t yre[2][NBB], yim[2][NBB];
+  acc_t yre[XB][NBB], yim[XB][NBB];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < NBB; ++y) {
       yre[x][y] = acc_t{0, 0, 0, 0};
       yim[x][y] = acc_t{0, 0, 0, 0};
     }
-  for (int ac = 0; ac < na; ac += 64) {
-    for (int e = threadIdx.x; e < 64 * NBC; e += 256) {
+  for (int ac = 0; ac < na; ac += KC) {
+    for (int e = threadIdx.x; e < KC * NBC; e += 256) {
       const int aa = e / NBC, bb = e - aa * NBC;
       TAcc vr = 0, vi = 0;
       if (ac + aa < na && b0 + bb < nb) {
@@ -342,15 +379,15 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
       cs_im[aa][bb] = vi;
     }
     __syncthreads();
-    const int steps = (na - ac) < 64 ? (na - ac + 3) / 4 : 16;
+    const int steps = (na - ac) < KC ? (na - ac + 3) / 4 : KC / 4;
     // four 4-orbital steps per group: all their A loads are issued first
     for (int st0 = 0; st0 < steps; st0 += 4) {
-      TAcc xr[4][2], xi[4][2];
+      TAcc xr[4][XB], xi[4][XB];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int a = ac + 4 * (st0 + u) + kq;
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
+        for (int x = 0; x < XB; ++x) {
           const long r = rt0 + 16 * x + r16;
           cx<TIn> v = {TIn(0), TIn(0)};
           if (st0 + u < steps && a < na && r < K) v = A[(size_t)a * lda + r];
@@ -367,7 +404,7 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
           const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
           const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
 #pragma unroll
-          for (int x = 0; x < 2; ++x) {
+          for (int x = 0; x < XB; ++x) {
             yre[x][y] = mfma4(xr[u][x], cr, yre[x][y]);
             yre[x][y] = mfma4(xi[u][x], -ci, yre[x][y]);
             yim[x][y] = mfma4(xr[u][x], ci, yim[x][y]);
@@ -379,7 +416,7 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < XB; ++x)
 #pragma unroll
     for (int y = 0; y < NBB; ++y) {
       const int b = b0 + 16 * y + r16;
@@ -392,51 +429,171 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
     }
 }
 
+// Expansion product with all of C resident in LDS (n_a <= kNnResA): a
+// persistent grid of one 8-wave workgroup per CU stages its 16 NBB columns of
+// C once, then every wave walks 16 XB-row tiles of Y with a stride of the
+// whole grid, so the staging is paid once per CU instead of once per tile.
+// The grid-row loads run R steps (4 orbitals each) ahead of the MFMAs.
+constexpr int kNnResA = 80;
+
+template <typename TIn, typename TAcc, int NBB>
+__global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__ A, long lda,
+                                                     int na, const cx<double>* __restrict__ C,
+                                                     int ldc, int nb, cx<TIn>* __restrict__ Y,
+                                                     long ldy, long K) {
+  typedef typename Acc4<TAcc>::type acc_t;
+  constexpr int XB = NnShape<TAcc>::XB;
+  constexpr int NBC = 16 * NBB;
+  constexpr int R = 8;
+  __shared__ TAcc cs_re[kNnResA][NBC];
+  __shared__ TAcc cs_im[kNnResA][NBC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = lane >> 4;
+  const int b0 = blockIdx.y * NBC;
+  const int na4 = (na + 3) & ~3;
+  for (int e = threadIdx.x; e < na4 * NBC; e += blockDim.x) {
+    const int aa = e / NBC, bb = e - aa * NBC;
+    TAcc vr = 0, vi = 0;
+    if (aa < na && b0 + bb < nb) {
+      const cx<double> cv = C[aa + (size_t)(b0 + bb) * ldc];
+      vr = (TAcc)cv.x;
+      vi = (TAcc)cv.y;
+    }
+    cs_re[aa][bb] = vr;
+    cs_im[aa][bb] = vi;
+  }
+  __syncthreads();
+  const int nsteps = na4 / 4;
+  const long ntiles = (K + 16 * XB - 1) / (16 * XB);
+  const int nwaves = blockDim.x >> 6;
+  for (long tile = (long)blockIdx.x * nwaves + wave; tile < ntiles;
+       tile += (long)gridDim.x * nwaves) {
+    const long rt0 = tile * 16 * XB;
+    acc_t yre[XB][NBB], yim[XB][NBB];
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < NBB; ++y) {
+        yre[x][y] = acc_t{0, 0, 0, 0};
+        yim[x][y] = acc_t{0, 0, 0, 0};
+      }
+    cx<TIn> buf[R][XB];
+    auto load = [&](cx<TIn> (&v)[XB], int st) {
+      const int a = 4 * st + kq;
+#pragma unroll
+      for (int x = 0; x < XB; ++x) {
+        const long r = rt0 + 16 * x + r16;
+        v[x] = {TIn(0), TIn(0)};
+        if (st < nsteps && a < na && r < K) v[x] = A[(size_t)a * lda + r];
+      }
+    };
+#pragma unroll
+    for (int j = 0; j < R - 1; ++j) load(buf[j], j);
+    for (int st0 = 0; st0 < nsteps; st0 += R) {
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        load(buf[(j + R - 1) % R], st0 + j + R - 1);
+        const int st = st0 + j;
+        if (st < nsteps) {
+#pragma unroll
+          for (int y = 0; y < NBB; ++y) {
+            const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
+            const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
+#pragma unroll
+            for (int x = 0; x < XB; ++x) {
+              const TAcc xr = (TAcc)buf[j][x].x, xi = (TAcc)buf[j][x].y;
+              yre[x][y] = mfma4(xr, cr, yre[x][y]);
+              yre[x][y] = mfma4(xi, -ci, yre[x][y]);
+              yim[x][y] = mfma4(xr, ci, yim[x][y]);
+              yim[x][y] = mfma4(xi, cr, yim[x][y]);
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < XB; ++x)
+#pragma unroll
+      for (int y = 0; y < NBB; ++y) {
+        const int b = b0 + 16 * y + r16;
+        if (b >= nb) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const long r = rt0 + 16 * x + mfma_row<TAcc>(lane, v);
+          if (r < K) Y[(size_t)b * ldy + r] = {(TIn)yre[x][y][v], (TIn)yim[x][y][v]};
+        }
+      }
+  }
+}
+
 }  // namespace
 
-static void cn_split2(int na, int nb, long K, long* ks_out, long* kchunk_out) {
-  const long tiles = (long)((na + 31) / 32) * ((nb + 31) / 32);
-  long ks = (1024 + tiles - 1) / tiles;  // about 1024 workgroups
-  long kchunk = (K + ks - 1) / ks;
-  kchunk = (kchunk + 255) / 256 * 256;  // whole unrolled iterations, even
-  if (kchunk < 256) kchunk = 256;
-  ks = (K + kchunk - 1) / kchunk;
+// Workgroup shape and K split of a reduction product: TA x TB waves per
+// workgroup, at most max_waves (16 for the FP32 kernel, 12 for the BF16-split
+// one, 8 for FP64).  The K chunks are sized so that all workgroups run in one
+// round on the 256 CUs (as many per CU as its cu_waves resident waves allow):
+// a second, partial round would double the time.  Each chunk is a whole
+// number of unrolled steps (a multiple of 64 points).
+struct CnShape {
+  int ta, tb, gx, gy;
+  long ks, kchunk;
+};
+
+static CnShape cn_shape(int na, int nb, long K, int max_waves, int cu_waves) {
+  CnShape s;
+  const int wa = (na + 31) / 32, wb = (nb + 31) / 32;
+  s.ta = wa < 4 ? wa : 4;
+  s.tb = wb < max_waves / s.ta ? wb : max_waves / s.ta;
+  s.gx = (wa + s.ta - 1) / s.ta;
+  s.gy = (wb + s.tb - 1) / s.tb;
+  int per_cu = cu_waves / (s.ta * s.tb);
+  if (per_cu < 1) per_cu = 1;
+  long ks = 256L * per_cu / ((long)s.gx * s.gy);
   if (ks < 1) ks = 1;
-  *ks_out = ks;
-  *kchunk_out = kchunk;
+  long kchunk = (K + ks - 1) / ks;
+  kchunk = (kchunk + 63) / 64 * 64;
+  if (kchunk < 64) kchunk = 64;
+  ks = (K + kchunk - 1) / kchunk;
+  s.ks = ks < 1 ? 1 : ks;
+  s.kchunk = kchunk;
+  return s;
 }
 
 size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
-  long ks, kchunk;
-  cn_split2(na, nb, K, &ks, &kchunk);
-  return align_up((size_t)ks * na * nb * sizeof(cx<double>), 256);
+  const CnShape s32 = cn_shape(na, nb, K, 16, 16), s16 = cn_shape(na, nb, K, 12, 12);
+  const CnShape s64 = cn_shape(na, nb, K, 8, 12);
+  const size_t b32 = (size_t)(s32.ks > s16.ks ? s32.ks : s16.ks) * na * nb * sizeof(cx<float>);
+  const size_t b64 = (size_t)s64.ks * na * nb * sizeof(cx<double>);
+  return align_up(b32 > b64 ? b32 : b64, 256);
 }
 
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, bool bf16_split) {
-  long ks, kchunk;
-  cn_split2(na, nb, K, &ks, &kchunk);
+  const CnShape s = sizeof(T) == 8 ? cn_shape(na, nb, K, 8, 12)
+                    : bf16_split    ? cn_shape(na, nb, K, 12, 12)
+                                    : cn_shape(na, nb, K, 16, 16);
   ace_status st;
-  cx<double>* partial = (cx<double>*)ws_take(c, (size_t)ks * na * nb * sizeof(cx<double>), &st);
+  cx<T>* partial = (cx<T>*)ws_take(c, (size_t)s.ks * na * nb * sizeof(cx<T>), &st);
   if (!partial) return st;
-  const dim3 grid((na + 31) / 32, (nb + 31) / 32, (unsigned)ks);
+  const dim3 grid((unsigned)s.gx, (unsigned)s.gy, (unsigned)s.ks);
+  const dim3 block(64 * s.ta, s.tb);
   if constexpr (std::is_same<T, float>::value) {
     if (bf16_split) {
-      if ((st = launch(c, "cn_mfma_bf16x3", k_cn_mfma_bf16x3, grid, dim3(256), 0, A, lda, na, B,
-                       ldb, nb, K, kchunk, partial)) != ACE_OK)
+      if ((st = launch(c, "cn_mfma_bf16x3", k_cn_mfma_bf16x3, grid, block, 0, A, lda, na, B, ldb,
+                       nb, K, s.kchunk, partial)) != ACE_OK)
         return st;
-    } else if ((st = launch(c, "cn_mfma_f32", k_cn_mfma<float>, grid, dim3(256), 0, A, lda, na,
-                            B, ldb, nb, K, kchunk, partial)) != ACE_OK) {
+    } else if ((st = launch(c, "cn_mfma_f32", k_cn_mfma<float>, grid, block, 0, A, lda, na, B,
+                            ldb, nb, K, s.kchunk, partial)) != ACE_OK) {
       return st;
     }
   } else {
-    if ((st = launch(c, "cn_mfma_f64", k_cn_mfma<double>, grid, dim3(256), 0, A, lda, na, B, ldb,
-                     nb, K, kchunk, partial)) != ACE_OK)
+    if ((st = launch(c, "cn_mfma_f64", k_cn_mfma<double>, grid, block, 0, A, lda, na, B, ldb, nb,
+                     K, s.kchunk, partial)) != ACE_OK)
       return st;
   }
-  return launch(c, "reduce_partials", k_reduce_partials2, dim3((na * nb + 15) / 16), dim3(256), 0,
-                (const cx<double>*)partial, (int)ks, na, nb, alpha, C, ldc);
+  return launch(c, "reduce_partials", k_reduce_partials2<T>, dim3((na * nb + 63) / 64),
+                dim3(1024), 0, (const cx<T>*)partial, (int)s.ks, na, nb, alpha, C, ldc);
 }
 
 template <typename TIn, typename TAcc>
@@ -445,9 +602,20 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
                               long K) {
   const int nbb = nb <= 16 ? 1 : nb <= 32 ? 2 : nb <= 48 ? 3 : nb <= 80 && nb > 64 ? 5 : 4;
   const dim3 block(256);
+  const bool resident = na <= kNnResA;
+  const unsigned gy = (unsigned)((nb + 16 * nbb - 1) / (16 * nbb));
 #define ACE_NN(NBBV)                                                                           \
   case NBBV: {                                                                                 \
-    const dim3 grid((unsigned)((K + 127) / 128), (unsigned)((nb + 16 * NBBV - 1) / (16 * NBBV))); \
+    if (resident) {                                                                            \
+      const long tiles = (K + 16 * NnShape<TAcc>::XB - 1) / (16 * NnShape<TAcc>::XB);          \
+      long gx = (tiles + 7) / 8;                                                               \
+      const long cap = (256 + gy - 1) / gy;                                                    \
+      if (gx > cap) gx = cap;                                                                  \
+      return launch(c, name, k_nn_mfma_res<TIn, TAcc, NBBV>, dim3((unsigned)gx, gy), dim3(512), \
+                    0, A, lda, na, C, ldc, nb, Y, ldy, K);                                     \
+    }                                                                                          \
+    const long rows = NnShape<TAcc>::ROWS;                                                    \
+    const dim3 grid((unsigned)((K + rows - 1) / rows), gy);                                    \
     return launch(c, name, k_nn_mfma<TIn, TAcc, NBBV>, grid, block, 0, A, lda, na, C, ldc, nb, Y, \
                   ldy, K);                                                                     \
   }

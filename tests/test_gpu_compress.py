@@ -124,3 +124,22 @@ def test_config1_full_fp64(ace):
     assert rel(to_np(Wg), W) <= 1e-10
     assert rel(to_np(xig), xi) <= 1e-10
     assert abs(e - gold["E_X_coulomb"]) <= 1e-10 * abs(gold["E_X_coulomb"])
+
+
+@pytest.mark.parametrize("nocc,nband", [(50, 88), (60, 100)])
+def test_compress_large_bands_both_factorisation_paths(ace, nocc, nband):
+    # n_band <= 88 factorises in LDS, larger n_band in global scratch
+    import torch
+    n, L = 16, 7.5
+    psi = synth.smooth_orbitals(n, L, nband, seed=nband)
+    g = ogrid(n, L, "erfc", 0.4)
+    W = O.build_W(psi[:nocc], psi, g)
+    _, Lc, xi = O.compress(psi, W, g)
+    gg = ggrid(n, L, "erfc", 0.4)
+    info = torch.full((1,), -3, dtype=torch.int32, device="cuda")
+    xig, Lg = ace.compress(to_gpu(psi, "fp64"), to_gpu(W, "fp64"), gg, "fp64", want_L=True,
+                           info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert rel(Lg.cpu().numpy(), Lc) <= 1e-10
+    assert rel(to_np(xig), xi) <= 1e-10
