@@ -31,6 +31,13 @@ WORKLOADS = {
     "cfg3": dict(n=72, L=30.8, nocc=216, nband=256, nx=256, kind="erfc", mu=0.106, prec="fp32",
                  desc="72^3 grid, L=30.8 bohr, N_occ=216, N_band=256, FP32 FFTs, FP64 "
                       "compression, erfc mu=0.106"),
+    "cfg4": dict(n=48, L=20.64, nocc=0, nband=0, nx=0, kind="coulomb", mu=0.0, prec="fp32",
+                 desc="48 independent instances (n in {32,40,48,64}, N_occ in [16,128], "
+                      "N_band = N_occ + 16, L = 0.43 n), one HIP-graph launch per step: "
+                      "build W and compress, FP32 FFTs"),
+    "cfg5": dict(n=64, L=27.0, nocc=128, nband=128, nx=0, kind="coulomb", mu=0.0, prec="fp32",
+                 desc="autograd E_X(phi) forward + hand-written backward, 64^3 grid, "
+                      "L=27 bohr, N_occ=128, complex64"),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -117,6 +124,10 @@ def main():
     cfg = dict(WORKLOADS[args.workload])
     if args.prec:
         cfg["prec"] = args.prec
+    if args.workload == "cfg4":
+        return run_batched(args, cfg)
+    if args.workload == "cfg5":
+        return run_autograd(args, cfg)
     prec = cfg["prec"]
     n, L, nocc, nband, nx = cfg["n"], cfg["L"], cfg["nocc"], cfg["nband"], cfg["nx"]
     grid = ace.Grid.cubic(n, L, cfg["kind"], cfg["mu"])
@@ -297,6 +308,136 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def _timed_loop(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _base_record(args, cfg, metric, value, unit, ms, dtype, config, roofline, extra):
+    return {"metric": metric, "value": round(value, 1), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roofline, "extra": extra}
+
+
+def run_batched(args, cfg):
+    """48 independent instances; one step = ace_build_batched (W and xi of every
+    instance) replayed from its HIP graph."""
+    import concurrent.futures as cf
+
+    import torch
+
+    from paper_1601_07159_amd import ace, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    specs = synth.batched_instances()
+    log("bench: cfg4: generating 48 instances")
+    with cf.ThreadPoolExecutor(8) as ex:
+        orbs = list(ex.map(synth.instance_orbitals, specs))
+    insts, pairs, transformed, fft_bytes = [], 0, 0, 0
+    for sp, psi in zip(specs, orbs):
+        x = torch.from_numpy(psi).to(dev, torch.complex64).reshape(sp["nband"], -1)
+        g = ace.Grid.cubic(sp["n"], sp["L"])
+        insts.append(dict(grid=g, phi=x[:sp["nocc"]], psi=x, W=torch.empty_like(x),
+                          xi=torch.empty_like(x),
+                          info=torch.zeros(1, dtype=torch.int32, device=dev)))
+        p = sp["nocc"] * sp["nband"]
+        tr = sp["nocc"] * (sp["nocc"] + 1) // 2 + sp["nocc"] * (sp["nband"] - sp["nocc"])
+        pairs += p
+        transformed += tr
+        fft_bytes += (3 * tr + p) * g.ng * 8
+    del orbs
+    ctx = ace.Context(0)
+    nbr = 4
+    ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32", n_branches=nbr),
+                     args.steps, args.warmup) * 1e3
+    bad = [k for k, d in enumerate(insts) if int(d["info"].item()) != 0]
+    achieved = fft_bytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "all FFT passes of the batch (graph replay)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": fft_bytes, "avg_launch_ms": round(ms, 4)}
+    extra = {"instances": len(insts), "branches": nbr, "pairs_per_step": pairs,
+             "transformed_pairs_per_step": transformed, "failed_cholesky": bad,
+             "fft_roofline_ms": fft_bytes / (HBM_PEAK_GBS * 1e9) * 1e3}
+    config = {"workload": f"cfg4: {cfg['desc']}", "precision": "fp32",
+              "instances": len(insts), "pairs_per_step": pairs, "parallelism": "single GPU"}
+    out = _base_record(args, cfg, "pair Poisson solves/s (batched ACE build, 48 instances)",
+                       pairs / (ms * 1e-3), "pair solves/s", ms, "f32", config, roofline, extra)
+    if not args.no_cpu:
+        sp = specs[0]
+        out["cpu_baseline"] = cpu_baseline(dict(n=sp["n"], L=sp["L"], nocc=sp["nocc"],
+                                                nband=sp["nband"], kind="coulomb", mu=0.0))
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def run_autograd(args, cfg):
+    """One step = E_X(phi) forward (pair spectra i <= j, Parseval sum) plus the
+    hand-written backward dE/dphi* (W = V_X[phi] phi recomputed)."""
+    import torch
+
+    from paper_1601_07159_amd import ace, synth
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, L, nocc = cfg["n"], cfg["L"], cfg["nocc"]
+    grid = ace.Grid.cubic(n, L)
+    log("bench: cfg5: generating orbitals")
+    phi0 = torch.from_numpy(synth.smooth_orbitals(n, L, nocc, seed=0)).to(
+        dev, torch.complex64).reshape(nocc, -1)
+    phi = phi0.clone().requires_grad_(True)
+    ctx = ace.context(0)
+
+    def step():
+        phi.grad = None
+        e = ace.ExchangeEnergy.apply(phi, grid, "fp32")
+        e.backward()
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    ms = _timed_loop(step, args.steps, 0) * 1e3
+    prof = ctx.profile_report()
+    ctx.profile(False)
+    fwd_pairs = nocc * (nocc + 1) // 2
+    bwd_pairs = nocc * nocc
+    solves = fwd_pairs + bwd_pairs
+    ng = grid.ng
+    # per-kernel pairs per step: forward energy = slab + energy pencil pass on
+    # the triangle; backward = build with the i <-> j symmetry (triangle only)
+    units = {"pair_fwd_slab": 1, "plane_kernel": 2, "pencil_accum": 1, "pencil_energy": 1}
+    per_step = {"pair_fwd_slab": 2 * fwd_pairs, "plane_kernel": fwd_pairs,
+                "pencil_accum": bwd_pairs, "pencil_energy": fwd_pairs}
+    dom = max(units, key=lambda k: prof.get(k, {"ms": 0})["ms"])
+    d = prof[dom]
+    avg_ms = d["ms"] / d["launches"]
+    ppl = per_step[dom] * args.steps / d["launches"]
+    achieved = units[dom] * ng * 8 * ppl / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "algorithmic_bytes_per_launch": round(units[dom] * ng * 8 * ppl),
+                "avg_launch_ms": round(avg_ms, 4), "pairs_per_launch": ppl}
+    extra = {"forward_pairs": fwd_pairs, "backward_pairs": bwd_pairs,
+             "per_kernel": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 5)}
+                            for k, v in prof.items()}}
+    config = {"workload": f"cfg5: {cfg['desc']}", "precision": "fp32", "grid": n, "L_bohr": L,
+              "n_occ": nocc, "solves_per_step": solves, "parallelism": "single GPU"}
+    out = _base_record(args, cfg, "pair Poisson solves/s (E_X forward + backward)",
+                       solves / (ms * 1e-3), "pair solves/s", ms, "f32", config, roofline, extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(dict(cfg, nband=nocc))
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -95,8 +95,9 @@ size_t gemm_cn_scratch_bytes(int na, int nb, long K);
 // Blocking of the build: A occupied orbitals x B bands per pair block, or the
 // symmetric occupied triangle; `bytes` is the workspace the build takes.
 struct BuildPlan {
-  int A, B;
-  bool sym;
+  int A, B;       // rectangle chunks: A orbitals x B bands
+  bool sym;       // i <-> j symmetry on the occupied block
+  int symblk;     // 0: the whole occupied triangle is one chunk; else block size
   size_t pairs_alloc;
   size_t bytes;
 };
@@ -104,6 +105,12 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t elem_bytes, int nocc, 
                      bool psi_starts_with_phi);
 // Workspace the compression takes for n_band vectors.
 size_t compress_ws_bytes(int nb, long ng);
+// Workspace of the orthonormalisation of n vectors (element size eb).
+size_t orth_ws_bytes(int n, long ng, size_t eb);
+// Direct exchange energy: pairs per chunk and workspace.
+long energy_chunk(ace_ctx c, const GridInfo& g, size_t eb, int nocc);
+size_t energy_direct_ws_bytes(ace_ctx c, const GridInfo& g, size_t eb, int nocc);
+size_t default_pair_budget_bytes();
 
 // Profiling hooks around one launch.
 void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0);

@@ -62,6 +62,13 @@ void* ws_take(ace_ctx c, size_t bytes, ace_status* st) {
   return p;
 }
 
+size_t orth_ws_bytes(int n, long ng, size_t eb) {
+  const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
+  const size_t tmp = align_up((size_t)n * ng * eb, 256);
+  const size_t scr = align_up(chol_scratch_elems(n) * sizeof(cx<double>), 256);
+  return 2 * mat + scr + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, ng);
+}
+
 size_t compress_ws_bytes(int nb, long ng) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
   const size_t scr = align_up(chol_scratch_elems(nb) * sizeof(cx<double>), 256);
@@ -247,7 +254,7 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
   const size_t tmp = align_up((size_t)n * g.ng * sizeof(cx<T>), 256);
   const size_t scr = align_up(chol_scratch_elems(n) * sizeof(cx<double>), 256);
-  ACE_TRY(ws_begin(c, 2 * mat + scr + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, g.ng)));
+  ACE_TRY(ws_begin(c, orth_ws_bytes(n, g.ng, sizeof(cx<T>))));
   ace_status st = ACE_OK;
   cx<double>* S = (cx<double>*)ws_take(c, mat, &st);
   cx<double>* Xs = (cx<double>*)ws_take(c, scr, &st);
@@ -387,16 +394,18 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   ACE_TRY(check_grid(c, grid, prec, &g));
   if (max_nocc < 1 || max_nband < 1 || max_nx < 0) return fail(c, ACE_E_ARG, "sizes");
   const size_t eb = elem_bytes(prec);
-  const size_t pair_bytes = (size_t)g.ng * eb;
-  const size_t budget = c->pair_budget ? c->pair_budget : ((size_t)2 << 30);
-  size_t pairs = std::max<size_t>(1, budget / pair_bytes);
-  pairs = std::min<size_t>(pairs, (size_t)max_nocc * max_nband);
-  size_t need = align_up(pairs * pair_bytes, 256) + align_up((size_t)g.ng * 8, 256) +
-                align_up((size_t)max_nocc * (max_nocc + 1) / 2 * 4096 * 8, 256);
+  // the largest workspace any call with these sizes takes (so that later
+  // calls, also under graph capture, need no allocation)
   const int nmax = std::max(max_nband, std::max(max_nx, max_nocc));
-  need = std::max(need, 3 * align_up((size_t)nmax * nmax * 16, 256) + 512 +
-                            align_up((size_t)nmax * g.ng * eb, 256) +
-                            gemm_cn_scratch_bytes(nmax, nmax, g.ng));
+  const size_t mat = align_up((size_t)nmax * nmax * sizeof(cx<double>), 256);
+  size_t need = std::max(plan_build(c, g, eb, max_nocc, max_nband, true).bytes,
+                         plan_build(c, g, eb, max_nocc, max_nband, false).bytes);
+  need = std::max(need, plan_build(c, g, eb, max_nocc, max_nocc, true).bytes);
+  need = std::max(need, compress_ws_bytes(max_nband, g.ng));
+  need = std::max(need, orth_ws_bytes(nmax, g.ng, eb));
+  need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), g.ng));
+  need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, max_nocc, g.ng));
+  need = std::max(need, energy_direct_ws_bytes(c, g, eb, max_nocc));
   return ws_begin(c, need);
 }
 

@@ -20,6 +20,8 @@
 // folded into the kernel table K'(G) = -scale K(G) / N_g.
 #include <cmath>
 
+#include <vector>
+
 #include "ace_internal.h"
 
 namespace ace {
@@ -72,7 +74,8 @@ inline unsigned xcd_pad(long count) { return (unsigned)((count + kXcds - 1) / kX
 
 // Pair of block-local index p.
 //  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
-//  mode 1: upper triangle i <= j, global triangle index p0 + p (row-major in j)
+//  mode 1: upper triangle i <= j of a diagonal block starting at i0 (= j0),
+//          block triangle index p0 + p (row-major in j)
 __device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0, long p, int* i,
                                         int* j) {
   if (mode == 0) {
@@ -83,8 +86,8 @@ __device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0
     long jj = (long)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
     while (jj * (jj + 1) / 2 > g) --jj;
     while ((jj + 1) * (jj + 2) / 2 <= g) ++jj;
-    *j = (int)jj;
-    *i = (int)(g - jj * (jj + 1) / 2);
+    *j = j0 + (int)jj;
+    *i = i0 + (int)(g - jj * (jj + 1) / 2);
   }
 }
 
@@ -325,17 +328,23 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
 }
 
 // Pencil pass with accumulation: one thread per (x0, x2) pencil along axis 1,
-// 64 pencils per workgroup, one band j per workgroup row of the grid.  Loops
-// over the occupied orbitals i of the block: inverse FFT along axis 1, multiply
-// by phi_i, accumulate into a thread-private LDS column; w_j is written once
+// 64 pencils per workgroup, one band per workgroup row of the grid.  Loops
+// over the orbitals i of the block: inverse FFT along axis 1, multiply by
+// phi_i, accumulate into a thread-private LDS column; the band is written once
 // per block.  Lanes hold consecutive pencils, so every global access is a
 // contiguous row; no barrier is needed anywhere.
+// Band j = j0 + b, orbital i = i0 + a; the spectrum of the pair comes from
+//  mode 0: a rectangle chunk (i0 + a, j0 + b) at index a + A b;
+//  mode 1: the triangle chunk of a diagonal block (i0 = j0): pairs i <= j at
+//          local index j'(j'+1)/2 + i', and u_ij = conj(u_ji) for i > j;
+//  mode 2: a rectangle chunk stored the other way round, (j, i) at index
+//          b + nbc a, read conjugated (u_ij = conj(u_ji)).
 template <int N, typename T>
 __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ phi, long ldphi,
                                                      const cx<T>* __restrict__ buf,
                                                      cx<T>* __restrict__ W, long ldW, int i0,
                                                      int A, int j0, int nbc, int accumulate,
-                                                     int sym) {
+                                                     int mode) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   __shared__ cx<T> acc[N * 64];
@@ -354,11 +363,20 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
   for (int k = 0; k < N; ++k) acc[k * 64 + t] = cx<T>{T(0), T(0)};
   const int j = j0 + b;
   for (int a = 0; a < A; ++a) {
-    // sym: the buffer holds only the pairs i <= j of the occupied block (upper
-    // triangle, index j(j+1)/2 + i); u_ij for i > j is conj(u_ji).
     const int i = i0 + a;
-    const size_t pidx = !sym ? (size_t)a + (size_t)A * b
-                             : (i <= j ? (size_t)j * (j + 1) / 2 + i : (size_t)i * (i + 1) / 2 + j);
+    size_t pidx;
+    bool conj_u;
+    if (mode == 0) {
+      pidx = (size_t)a + (size_t)A * b;
+      conj_u = false;
+    } else if (mode == 1) {
+      const int il = a, jl = b;  // local indices in the diagonal block
+      pidx = il <= jl ? (size_t)jl * (jl + 1) / 2 + il : (size_t)il * (il + 1) / 2 + jl;
+      conj_u = il > jl;
+    } else {
+      pidx = (size_t)b + (size_t)nbc * a;
+      conj_u = true;
+    }
     const cx<T>* src = buf + pidx * N * NN + off;
     const cx<T>* fp = phi + (size_t)i * ldphi + off;
     cx<T> v[N];
@@ -368,7 +386,7 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
 #pragma unroll
     for (int k = 0; k < N; ++k) f[k] = fp[k * N];
     fft_line<N, +1, T>(v);
-    if (sym && i > j) {
+    if (conj_u) {
 #pragma unroll
       for (int k = 0; k < N; ++k) v[k].y = -v[k].y;
     }
@@ -428,7 +446,26 @@ __global__ __launch_bounds__(256) void k_pencil_energy(const cx<T>* __restrict__
   }
 }
 
-// Deterministic single-workgroup sum: *out = s * sum(x[0..n)).
+// Deterministic two-stage sum, *out = s * sum(x[0..n)): kSumBlocks
+// workgroups each sum a contiguous range into y[b] (fixed order, tree), then
+// one workgroup sums y.
+constexpr int kSumBlocks = 256;
+__global__ __launch_bounds__(1024) void k_sum_blocks(const double* __restrict__ x, long n,
+                                                     double* __restrict__ y) {
+  __shared__ double red[1024];
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long beg = (long)blockIdx.x * per, end = beg + per < n ? beg + per : n;
+  double acc = 0.0;
+  for (long k = beg + threadIdx.x; k < end; k += 1024) acc += x[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[blockIdx.x] = red[0];
+}
+
 __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ x, long n,
                                                      double s, double* __restrict__ out) {
   __shared__ double red[1024];
@@ -446,6 +483,24 @@ __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ 
 size_t default_pair_budget() { return (size_t)2 << 30; }
 
 }  // namespace
+
+size_t default_pair_budget_bytes() { return default_pair_budget(); }
+
+// Pairs per chunk of the direct energy (triangle i <= j in budget-sized chunks).
+long energy_chunk(ace_ctx c, const GridInfo& g, size_t eb, int nocc) {
+  const long total = (long)nocc * (nocc + 1) / 2;
+  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
+  const long chunk = std::max<long>(1, (long)(budget / ((size_t)g.ng * eb)));
+  return std::min(chunk, total);
+}
+
+size_t energy_direct_ws_bytes(ace_ctx c, const GridInfo& g, size_t eb, int nocc) {
+  const long total = (long)nocc * (nocc + 1) / 2;
+  const long tiles = ((long)g.n * g.n + 63) / 64;
+  return align_up((size_t)g.ng * (eb / 2), 256) +
+         align_up(((size_t)total * tiles + kSumBlocks) * sizeof(double), 256) +
+         align_up((size_t)energy_chunk(c, g, eb, nocc) * g.ng * eb, 256);
+}
 
 BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nband,
                      bool psi_starts_with_phi) {
@@ -466,19 +521,39 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
   // (N^2 / 64) * B one-wave workgroups, each looping over the i block, and W is
   // read-modified-written once per i block.
   // Pair symmetry: when psi's first n_occ orbitals are phi, u_ji = conj(u_ij)
-  // on the occupied block and only its triangle i <= j needs FFTs.  Needs the
-  // whole triangle in flight at once.
+  // on the occupied block and only its triangle i <= j needs FFTs.  When the
+  // whole triangle fits the budget it is one chunk; otherwise the occupied
+  // orbitals are split into blocks of b, and each block pair I <= J is one
+  // chunk (the triangle of I for I = J, the rectangle I x J otherwise) whose
+  // spectra serve the bands of J and, conjugated, those of I.
   const long tri = (long)nocc * (nocc + 1) / 2;
-  pl.sym = c->use_symmetry && psi_starts_with_phi && nocc >= 2 && tri <= maxpairs &&
-           (long)g.n * tri < (1L << 31);
-  // the rectangular blocks cover the bands after the triangle (all of them
-  // without symmetry)
+  pl.sym = c->use_symmetry && psi_starts_with_phi && nocc >= 2;
+  pl.symblk = 0;
+  long sym_alloc = 0;
+  if (pl.sym) {
+    if (tri <= maxpairs && (long)g.n * tri < (1L << 31)) {
+      sym_alloc = tri;
+    } else {
+      long bmax = (long)std::sqrt((double)maxpairs);
+      while ((bmax + 1) * (bmax + 1) <= maxpairs) ++bmax;
+      while (bmax > 1 && bmax * bmax > maxpairs) --bmax;
+      if (bmax < 2) {
+        pl.sym = false;  // budget below a 2 x 2 block
+      } else {
+        const long nblk = (nocc + bmax - 1) / bmax;
+        pl.symblk = (int)((nocc + nblk - 1) / nblk);  // even blocks, last may be short
+        sym_alloc = (long)pl.symblk * pl.symblk;
+      }
+    }
+  }
+  // the rectangular blocks cover the bands after the occupied block (all of
+  // them without symmetry)
   const int nrect = std::max(1, pl.sym ? nband - nocc : nband);
   int B = jblock > 0 ? (int)std::min<long>(nrect, jblock) : nrect;
   B = (int)std::max<long>(1, std::min<long>(B, maxpairs));
   pl.B = B;
   pl.A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
-  pl.pairs_alloc = std::max<size_t>((size_t)pl.A * pl.B, pl.sym ? (size_t)tri : 0);
+  pl.pairs_alloc = std::max<size_t>((size_t)pl.A * pl.B, (size_t)sym_alloc);
   pl.bytes = align_up((size_t)g.ng * std::max<size_t>(eb / 2, 4), 256) +
              align_up(pl.pairs_alloc * pair_bytes, 256);
   return pl;
@@ -494,14 +569,18 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
                 g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
 }
 
-// Line shape of the slab and plane passes: one thread per line (better for
-// FP32) or a quad per line (far fewer registers; no spills for FP64 at large
-// N).  The tuning knob ACE_TUNE_FFT_SHAPE overrides: 1 = thread, 4 = quad.
+// Line shape of the slab and plane passes: one thread per line or a quad per
+// line (far fewer registers: no spills for FP64 at large N, occupancy 4
+// instead of 1 for FP32 at N >= 64).  Defaults from timings on the MI355X:
+// FP32 slab pass quad only at N = 72, FP32 plane pass quad from N = 64, FP64
+// quad from N = 48.  The tuning knob ACE_TUNE_FFT_SHAPE overrides both
+// passes: 1 = thread, 4 = quad.
 template <int N, typename T>
-bool use_quad(ace_ctx c) {
+bool use_quad(ace_ctx c, bool plane_pass) {
   if (c->fft_shape == 1) return false;
   if (c->fft_shape == 4) return true;
-  return sizeof(T) == 8 && N >= 48;
+  if (sizeof(T) == 8) return N >= 48;
+  return plane_pass ? N >= 64 : N >= 72;
 }
 
 template <int N, typename T>
@@ -545,20 +624,63 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
   if (!Kt || !buf) return st;
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
-  const bool quad = use_quad<N, T>(c);
+  const bool quad = use_quad<N, T>(c, false), quad_p = use_quad<N, T>(c, true);
   int jstart = 0;
-  if (sym) {
+  const dim3 pgrid_occ(xcd_pad((long)TILES * nocc));
+  if (sym && pl.symblk == 0) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
     // accumulates all i from it (u_ij = conj(u_ji))
     const long tri = (long)nocc * (nocc + 1) / 2;
     if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) !=
         ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, quad, buf, Kt, (int)tri)) != ACE_OK) return st;
-    if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nocc)),
-                     dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, 0, nocc, 0, nocc, 0,
-                     1)) != ACE_OK)
+    if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)tri)) != ACE_OK) return st;
+    if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, pgrid_occ, dim3(64), 0, phi, ldphi,
+                     (const cx<T>*)buf, W, ldW, 0, nocc, 0, nocc, 0, 1)) != ACE_OK)
       return st;
+    jstart = nocc;
+  } else if (sym) {
+    // occupied block in blocks of b: chunk (I, J), I <= J, in a fixed order;
+    // a band is written by its first contribution and accumulated afterwards
+    const int b = pl.symblk, nblk = (nocc + b - 1) / b;
+    std::vector<char> started(nblk, 0);
+    for (int J = 0; J < nblk; ++J)
+      for (int I = 0; I <= J; ++I) {
+        const int i0 = I * b, ni = std::min(b, nocc - i0);
+        const int j0 = J * b, nj = std::min(b, nocc - j0);
+        if (I == J) {
+          const int np = ni * (ni + 1) / 2;
+          if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 1, i0, 1, i0, 0L, np)) !=
+              ACE_OK)
+            return st;
+          if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
+          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
+                           dim3(xcd_pad((long)TILES * ni)), dim3(64), 0, phi, ldphi,
+                           (const cx<T>*)buf, W, ldW, i0, ni, i0, ni, (int)started[I], 1)) !=
+              ACE_OK)
+            return st;
+          started[I] = 1;
+        } else {
+          const int np = ni * nj;
+          if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 0, i0, ni, j0, 0L, np)) !=
+              ACE_OK)
+            return st;
+          if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
+          // bands of J from the orbitals of I, then bands of I from those of J
+          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
+                           dim3(xcd_pad((long)TILES * nj)), dim3(64), 0, phi, ldphi,
+                           (const cx<T>*)buf, W, ldW, i0, ni, j0, nj, (int)started[J], 0)) !=
+              ACE_OK)
+            return st;
+          started[J] = 1;
+          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
+                           dim3(xcd_pad((long)TILES * ni)), dim3(64), 0, phi, ldphi,
+                           (const cx<T>*)buf, W, ldW, j0, nj, i0, ni, (int)started[I], 2)) !=
+              ACE_OK)
+            return st;
+          started[I] = 1;
+        }
+      }
     jstart = nocc;
   }
   for (int j0 = jstart; j0 < nband; j0 += B) {
@@ -569,7 +691,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
       if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) !=
           ACE_OK)
         return st;
-      if ((st = plane<N, T>(c, quad, buf, Kt, np)) != ACE_OK) return st;
+      if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
       if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * Bc)),
                        dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
                        i0 > 0 ? 1 : 0, 0)) != ACE_OK)
@@ -586,15 +708,11 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   constexpr int TILES = (NN + 63) / 64;
   const long total = (long)nocc * (nocc + 1) / 2;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
-  const size_t budget = c->pair_budget ? c->pair_budget : default_pair_budget();
-  long chunk = std::max<long>(1, (long)(budget / pair_bytes));
-  chunk = std::min(chunk, total);
+  const long chunk = energy_chunk(c, g, sizeof(cx<T>), nocc);
   const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
-  const size_t part_bytes = align_up((size_t)total * TILES * sizeof(double), 256);
+  const size_t part_bytes = align_up(((size_t)total * TILES + kSumBlocks) * sizeof(double), 256);
   ace_status st;
-  if ((st = ws_begin(c, kt_bytes + part_bytes + align_up((size_t)chunk * pair_bytes, 256))) !=
-      ACE_OK)
-    return st;
+  if ((st = ws_begin(c, energy_direct_ws_bytes(c, g, sizeof(cx<T>), nocc))) != ACE_OK) return st;
   T* Kt = (T*)ws_take(c, kt_bytes, &st);
   double* partial = (double*)ws_take(c, part_bytes, &st);
   cx<T>* buf = (cx<T>*)ws_take(c, (size_t)chunk * pair_bytes, &st);
@@ -602,15 +720,19 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
   for (long p0 = 0; p0 < total; p0 += chunk) {
     const int np = (int)std::min(chunk, total - p0);
-    if ((st = fwd_slab<N, T>(c, use_quad<N, T>(c), phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
+    if ((st = fwd_slab<N, T>(c, use_quad<N, T>(c, false), phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
                              np)) != ACE_OK)
       return st;
     if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(256), 0,
                      (const cx<T>*)buf, (const T*)Kt, p0, partial)) != ACE_OK)
       return st;
   }
-  return launch(c, "sum_scaled", k_sum_scaled, dim3(1), dim3(1024), 0, (const double*)partial,
-                total * TILES, -0.5 * g.dV / (double)g.ng, ex_dev);
+  double* blocks = partial + (size_t)total * TILES;
+  if ((st = launch(c, "sum_blocks", k_sum_blocks, dim3(kSumBlocks), dim3(1024), 0,
+                   (const double*)partial, total * TILES, blocks)) != ACE_OK)
+    return st;
+  return launch(c, "sum_scaled", k_sum_scaled, dim3(1), dim3(1024), 0, (const double*)blocks,
+                (long)kSumBlocks, -0.5 * g.dV / (double)g.ng, ex_dev);
 }
 
 }  // namespace

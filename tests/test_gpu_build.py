@@ -126,6 +126,31 @@ def test_build_W_pair_symmetry_matches_full(ace, prec):
     assert rel(W_sym, W_all) <= (1e-13 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("budget_pairs", [4, 9, 20, 30])
+def test_build_W_blocked_symmetry(ace, prec, budget_pairs):
+    # the occupied triangle (55 pairs) does not fit the pair budget: the
+    # occupied orbitals go in blocks of b (b^2 <= budget) and each block pair
+    # is one chunk serving both of its band blocks; compare with the oracle and
+    # with the build that transforms every pair
+    n, L, nocc, nband = 16, 6.5, 10, 13
+    psi = synth.smooth_orbitals(n, L, nband, seed=77)
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L), scale=0.5)
+    x = to_gpu(psi, prec)
+    g = ggrid(n, L)
+    ctx = ace.Context()
+    ctx.set_pair_budget(budget_pairs * n ** 3 * (16 if prec == "fp64" else 8))
+    W_blk = to_np(ctx.build_W(x[:nocc], x, g, prec, scale=0.5))
+    W_blk2 = to_np(ctx.build_W(x[:nocc], x, g, prec, scale=0.5))
+    ctx.set_tuning("symmetry", 0)
+    W_all = to_np(ctx.build_W(x[:nocc], x, g, prec, scale=0.5))
+    ctx.close()
+    assert rel(W_blk, ref) <= tol(prec)
+    assert rel(W_all, ref) <= tol(prec)
+    assert rel(W_blk, W_all) <= (1e-13 if prec == "fp64" else 1e-6)
+    assert np.array_equal(W_blk, W_blk2)   # fixed chunk order: deterministic
+
+
 def test_config2_full_size_sampled(ace):
     """48^3, L = 20.5, N_occ = 64, N_band = 80, mixed precision, in the bench's
     launch configuration: sampled columns of W against the oracle; xi and the
