@@ -104,6 +104,29 @@ __device__ __forceinline__ cx<T> root(int q) {
   return {T(kRoots<N>.c[q]), T(SIGN * kRoots<N>.s[q])};
 }
 
+// v * exp(SIGN 2 pi i q / N).  q is a constant once the stage loops are
+// unrolled, so the branches fold away; the roots 1, +-i, -1 and the eighth
+// roots (1 +- i)/sqrt(2) cost no multiply or two, not the four of a general
+// complex product (a product by an exact 1 or 0 is not removed by the
+// compiler, since x * 0 is not 0 for every x in IEEE arithmetic).
+template <int N, int SIGN, typename T>
+__device__ __forceinline__ cx<T> twiddle(cx<T> v, int q) {
+  if (q == 0) return v;
+  if (4 * q == N) return mul_si<SIGN>(v);
+  if (2 * q == N) return cx<T>{-v.x, -v.y};
+  if (4 * q == 3 * N) return mul_si<-SIGN>(v);
+  if (8 * q == N || 8 * q == 3 * N || 8 * q == 5 * N || 8 * q == 7 * N) {
+    // exp(SIGN i pi m / 4), m odd: ((+-1) + SIGN (+-1) i) / sqrt(2)
+    const T r = T(0.70710678118654752440);
+    const int m = 8 * q / N;
+    const T cr = (m == 1 || m == 7) ? T(1) : T(-1);
+    const T ci = (m == 1 || m == 3) ? T(SIGN) : T(-SIGN);
+    // (cr + i ci)(x + i y) = (cr x - ci y) + i (cr y + ci x)
+    return cx<T>{r * (cr * v.x - ci * v.y), r * (cr * v.y + ci * v.x)};
+  }
+  return cmul(v, root<N, SIGN, T>(q));
+}
+
 // ---------------------------------------------------------------------------
 // Small DFTs on registers: v[k] <- sum_r v[r] exp(SIGN 2 pi i r k / R).
 template <int R, int S, typename T>
@@ -200,8 +223,10 @@ struct Plan;
 template <> struct Plan<2>   { template <template <int...> class F> using apply = F<2>; };
 template <> struct Plan<3>   { template <template <int...> class F> using apply = F<3>; };
 template <> struct Plan<4>   { template <template <int...> class F> using apply = F<4>; };
+template <> struct Plan<5>   { template <template <int...> class F> using apply = F<5>; };
 template <> struct Plan<6>   { template <template <int...> class F> using apply = F<3, 2>; };
 template <> struct Plan<10>  { template <template <int...> class F> using apply = F<5, 2>; };
+template <> struct Plan<9>   { template <template <int...> class F> using apply = F<3, 3>; };
 template <> struct Plan<18>  { template <template <int...> class F> using apply = F<3, 3, 2>; };
 template <> struct Plan<8>   { template <template <int...> class F> using apply = F<8>; };
 template <> struct Plan<12>  { template <template <int...> class F> using apply = F<4, 3>; };
@@ -231,7 +256,7 @@ __device__ __forceinline__ void stockham_stage(const cx<T>* in, cx<T>* out) {
     const int k = j % Ns;
     if (Ns > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], root<N, S, T>((k * r * (N / (Ns * R))) % N));
+      for (int r = 1; r < R; ++r) v[r] = twiddle<N, S, T>(v[r], (k * r * (N / (Ns * R))) % N);
     }
     SmallDft<R, S, T>::run(v);
     const int d = (j / Ns) * Ns * R + k;
@@ -262,11 +287,64 @@ struct RadixList {
   }
 };
 
+// Prime-factor (Good-Thomas) split N = N1 N2 with gcd(N1, N2) = 1: input
+// index n = (n1 N2 + n2 N1) mod N, output index k = CRT(k1 mod N1, k2 mod N2);
+// then exp(2 pi i n k / N) = exp(2 pi i n1 k1 / N1) exp(2 pi i n2 k2 / N2), so
+// the transform is N2 DFTs of length N1 and N1 of length N2 with no twiddle
+// factors between them (the index maps are register renamings).
+template <int N>
+struct PfaSplit {
+  static constexpr int n1 = 0, n2 = 0;
+};
+template <> struct PfaSplit<12> { static constexpr int n1 = 4, n2 = 3; };
+template <> struct PfaSplit<18> { static constexpr int n1 = 2, n2 = 9; };
+template <> struct PfaSplit<24> { static constexpr int n1 = 8, n2 = 3; };
+template <> struct PfaSplit<40> { static constexpr int n1 = 8, n2 = 5; };
+template <> struct PfaSplit<48> { static constexpr int n1 = 16, n2 = 3; };
+template <> struct PfaSplit<72> { static constexpr int n1 = 8, n2 = 9; };
+
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_line(cx<T>* v);
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_pfa(cx<T>* v) {
+  constexpr int N1 = PfaSplit<N>::n1, N2 = PfaSplit<N>::n2;
+  static_assert(N1 * N2 == N, "PFA split");
+  constexpr int E1 = N2 * inv_mod(N2 % N1, N1);  // = 1 mod N1, 0 mod N2
+  constexpr int E2 = N1 * inv_mod(N1 % N2, N2);  // = 0 mod N1, 1 mod N2
+  cx<T> a[N2][N1];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2)
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[(n1 * N2 + n2 * N1) % N];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) fft_line<N1, S, T>(a[n2]);
+  cx<T> b[N1][N2];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) b[k1][n2] = a[n2][k1];
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) fft_line<N2, S, T>(b[k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) v[(k1 * E1 + k2 * E2) % N] = b[k1][k2];
+}
+
 // In-place length-N DFT of a register array.
 template <int N, int S, typename T>
 __device__ __forceinline__ void fft_line(cx<T>* v) {
   if constexpr (N == 1) {
     (void)v;
+  } else if constexpr (PfaSplit<N>::n1 > 0) {
+    fft_pfa<N, S, T>(v);
   } else {
     Plan<N>::template apply<RadixList>::template run<N, S, T>(v);
   }
