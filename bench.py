@@ -31,6 +31,10 @@ WORKLOADS = {
     "cfg3": dict(n=72, L=30.8, nocc=216, nband=256, nx=256, kind="erfc", mu=0.106, prec="fp32",
                  desc="72^3 grid, L=30.8 bohr, N_occ=216, N_band=256, FP32 FFTs, FP64 "
                       "compression, erfc mu=0.106"),
+    "cfg2r": dict(n=48, L=20.5, nocc=64, nband=80, nx=80, kind="coulomb", mu=0.0, prec="real32",
+                  desc="48^3 grid, L=20.5 bohr, N_occ=64, N_band=80, real orbitals (Gamma "
+                       "point): two pair charges per complex64 FFT, BF16-split M, FP64 "
+                       "Cholesky/TRSM, Coulomb"),
     "cfg4": dict(n=48, L=20.64, nocc=0, nband=0, nx=0, kind="coulomb", mu=0.0, prec="fp32",
                  desc="48 independent instances (n in {32,40,48,64}, N_occ in [16,128], "
                       "N_band = N_occ + 16, L = 0.43 n), one HIP-graph launch per step: "
@@ -81,7 +85,10 @@ def cpu_baseline(cfg, seconds=10.0):
 
     import oracle as O
     from paper_1601_07159_amd import synth
-    psi = synth.smooth_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
+    if cfg.get("prec", "").startswith("real"):
+        psi = synth.real_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
+    else:
+        psi = synth.smooth_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
     phi = psi[:cfg["nocc"]]
     g = O.Grid.cubic(cfg["n"], cfg["L"], cfg["kind"], cfg["mu"])
     t0 = time.perf_counter()
@@ -104,7 +111,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "mixed", "real64", "real32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--copy-probe", action="store_true",
@@ -132,11 +139,16 @@ def main():
     n, L, nocc, nband, nx = cfg["n"], cfg["L"], cfg["nocc"], cfg["nband"], cfg["nx"]
     grid = ace.Grid.cubic(n, L, cfg["kind"], cfg["mu"])
     ng = grid.ng
-    cdt = torch.complex128 if prec == "fp64" else torch.complex64
-    sbytes = 16 if prec == "fp64" else 8
+    real = prec.startswith("real")
+    dtypes = {"fp64": torch.complex128, "real64": torch.float64, "real32": torch.float32}
+    cdt = dtypes.get(prec, torch.complex64)
+    ref_prec = "real64" if real else "fp64"
+    # bytes of one complex FFT element (real orbitals are transformed in pairs)
+    sbytes = 16 if prec in ("fp64", "real64") else 8
 
     log(f"bench: workload {args.workload} prec={prec}: generating inputs")
-    psi_np = synth.smooth_orbitals(n, L, nband, seed=0)
+    psi_np = (synth.real_orbitals(n, L, nband, seed=0) if real
+              else synth.smooth_orbitals(n, L, nband, seed=0))
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     psi_in = torch.from_numpy(psi_np).to(dev, cdt)
@@ -207,13 +219,21 @@ def main():
     #   pair_fwd_slab: write the slab spectra (inputs amortised over the pair block)
     #   plane_kernel:  read + write
     #   pencil_accum:  read (phi and W amortised over the pair block)
-    fft_units = {"pair_fwd_slab": 1, "plane_kernel": 2, "pencil_accum": 1}
+    fft_units = {"pair_fwd_slab": 1, "plane_kernel": 2, "pencil_accum": 1, "pair_fwd_real": 1,
+                 "pencil_accum_real": 1}
     # pairs each pass handles per step: with the i <-> j symmetry (psi starts
     # with phi) the forward and plane passes transform the occupied triangle
     # plus the rectangle of extra bands; the accumulate pass reads every pair
     sym = ctx.get_tuning("symmetry") == 1
-    transformed = (nocc * (nocc + 1) // 2 + nocc * (nband - nocc)) if sym else pairs
-    per_step = {"pair_fwd_slab": transformed, "plane_kernel": transformed, "pencil_accum": pairs}
+    if real:
+        # real orbitals: units of two pairs (orbitals 2m, 2m+1) for every band
+        transformed = (nocc + 1) // 2 * nband
+        per_step = {"pair_fwd_real": transformed, "plane_kernel": transformed,
+                    "pencil_accum_real": transformed}
+    else:
+        transformed = (nocc * (nocc + 1) // 2 + nocc * (nband - nocc)) if sym else pairs
+        per_step = {"pair_fwd_slab": transformed, "plane_kernel": transformed,
+                    "pencil_accum": pairs}
     dom = max(fft_units, key=lambda k: prof.get(k, {"ms": 0})["ms"])
     d = prof[dom]
     avg_ms = d["ms"] / d["launches"]
@@ -227,7 +247,7 @@ def main():
                 "algorithmic_bytes_per_launch": round(bytes_per_pair * pairs_per_launch),
                 "avg_launch_ms": round(avg_ms, 4), "pairs_per_launch": pairs_per_launch}
     build_ms = st_ms["build_W"]
-    build_bytes = (3 * transformed + pairs) * ng * sbytes
+    build_bytes = (3 * transformed + per_step.get("pencil_accum", transformed)) * ng * sbytes
     extra = {
         "stage_ms": {k: round(v, 4) for k, v in st_ms.items()},
         "build_pairs_per_s": pairs / (build_ms * 1e-3),
@@ -240,24 +260,25 @@ def main():
     }
 
     # errors vs an FP64 run on the same seed (outside the timed region)
-    if not args.no_fp64 and prec != "fp64":
+    if not args.no_fp64 and prec not in ("fp64", "real64"):
         log("bench: FP64 comparison run")
-        b64 = make_bufs(torch.complex128)
-        psi64 = torch.from_numpy(psi_np).to(dev, torch.complex128)
-        step("fp64", b64, psi64)
+        dt64 = dtypes[ref_prec]
+        b64 = make_bufs(dt64)
+        psi64 = torch.from_numpy(psi_np).to(dev, dt64)
+        step(ref_prec, b64, psi64)
         torch.cuda.synchronize()
         t = []
         for _ in range(max(2, min(args.steps, 5))):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            step("fp64", b64, psi64)
+            step(ref_prec, b64, psi64)
             e1.record()
             torch.cuda.synchronize()
             t.append(e0.elapsed_time(e1))
         extra["fp64_ms_per_step"] = float(np.median(t))
         stage_ev.clear()
-        step("fp64", b64, psi64, timed=True)
+        step(ref_prec, b64, psi64, timed=True)
         torch.cuda.synchronize()
         ev = stage_ev[-1]
         extra["fp64_stage_ms"] = {s: round(ev[k].elapsed_time(ev[k + 1]), 4)
@@ -266,7 +287,7 @@ def main():
             extra["fp64_stage_ms"]["apply"] * 1e-3) / 1e12
 
         def relerr(a, b):
-            a = a.to(torch.complex128)
+            a = a.to(b.dtype)
             return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
         extra["errors_vs_fp64"] = {
             "W": relerr(bufs["W"], b64["W"]),
@@ -295,7 +316,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16split"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16split", "real64": "f64",
+                  "real32": "f32+bf16split"}[prec],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {cfg['desc']}", "precision": prec,
                    "grid": n, "L_bohr": L, "n_occ": nocc, "n_band": nband, "n_x": nx,

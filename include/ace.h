@@ -18,6 +18,15 @@
  *         complex elements) and holds its N_g grid values in C order
  *         (index (x0 * n1 + x1) * n2 + x2).  This is an N_g x N column-major
  *         matrix with leading dimension ld.
+ * Real orbitals.  With ACE_REAL64 / ACE_REAL32 every orbital block (inputs
+ *         and outputs) holds N_g reals per orbital, ld counted in reals; ld
+ *         must be even and each orbital start aligned to two values.  The
+ *         build transforms two pair charges per complex FFT (phi_a psi_j +
+ *         i phi_b psi_j: both real, and the real even kernel keeps the two
+ *         potentials apart as real and imaginary parts).  Small matrices
+ *         (L_out) stay complex128 with zero imaginary parts.  Not available
+ *         for real orbitals: the direct energy form (xi == NULL), the batched
+ *         build and the tuner (ACE_E_UNSUPPORTED).
  * Inner product.  <f, g> = dV * sum_r conj(f(r)) g(r); orbitals are expected
  *         to satisfy <phi_i, phi_j> = delta_ij where the paper says so.
  * Ownership.  The caller owns every pointer passed in; the library never frees
@@ -51,8 +60,11 @@ typedef enum {
 typedef enum {
   ACE_FP64 = 0,   /* complex128 data; FFTs, products and factorisations in FP64 */
   ACE_FP32 = 1,   /* complex64 data; FFTs and apply in FP32; M, Cholesky, xi in FP64 */
-  ACE_MIXED = 2   /* complex64 data; FFTs and apply in FP32; M by BF16-split MFMA
+  ACE_MIXED = 2,  /* complex64 data; FFTs and apply in FP32; M by BF16-split MFMA
                      products with FP32 accumulation; Cholesky and xi in FP64 */
+  ACE_REAL64 = 3, /* real orbitals (the Gamma-point setting of Section 4): arrays of
+                     doubles; everything in FP64 */
+  ACE_REAL32 = 4  /* real orbitals, arrays of floats; arithmetic as ACE_MIXED */
 } ace_prec;
 
 typedef enum {

@@ -8,7 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libace.so")
 
 ACE_OK, ACE_E_ARG, ACE_E_NOT_PD, ACE_E_NOMEM, ACE_E_HIP, ACE_E_UNSUPPORTED = range(6)
-ACE_FP64, ACE_FP32, ACE_MIXED = 0, 1, 2
+ACE_FP64, ACE_FP32, ACE_MIXED, ACE_REAL64, ACE_REAL32 = 0, 1, 2, 3, 4
 ACE_COULOMB, ACE_ERFC = 0, 1
 
 EXPORTED = [

@@ -7,7 +7,9 @@ raises.
 
 Orbital blocks are complex tensors of shape (N, n0, n1, n2) (or (N, N_g)) whose
 last dimensions are contiguous; the stride of dim 0 is the C ABI's ``ld``.
-complex128 goes with FP64, complex64 with FP32 and MIXED.
+complex128 goes with FP64, complex64 with FP32 and MIXED; real orbitals
+(precisions "real64" / "real32") are float64 / float32 tensors of the same
+shapes.
 """
 from __future__ import annotations
 
@@ -17,9 +19,10 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import ACE_FP32, ACE_FP64, ACE_MIXED  # noqa: F401
+from ._lib import ACE_FP32, ACE_FP64, ACE_MIXED, ACE_REAL32, ACE_REAL64  # noqa: F401
 
-PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED}
+PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED, "real64": ACE_REAL64,
+        "real32": ACE_REAL32}
 _TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
               "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE}
 
@@ -73,7 +76,8 @@ def _prec(p) -> int:
 
 
 def _dtype_for(prec: int):
-    return torch.complex128 if prec == ACE_FP64 else torch.complex64
+    return {ACE_FP64: torch.complex128, ACE_REAL64: torch.float64,
+            ACE_REAL32: torch.float32}.get(prec, torch.complex64)
 
 
 def _block(t: torch.Tensor, prec: int, ng: int, what: str):

@@ -142,6 +142,12 @@ ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc
 template <typename T>
 ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
                               long ldphi, double* ex_dev);
+// Real orbitals (arrays of N_g reals): two pairs per complex transform.
+template <typename T>
+ace_status build_W_real_impl(ace_ctx c, const GridInfo& g, const T* phi, int nocc, long ldphi,
+                             const T* psi, int nband, long ldpsi, T* W, long ldW, double scale,
+                             const double* dscale = nullptr);
+BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband);
 
 // Argument checks shared by the entry points (api.hip).
 ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out);
@@ -156,16 +162,21 @@ Span span_of(const void* p, int count, long ld, long ng, size_t eb);
 bool overlap(Span a, Span b);
 
 // Compression of one instance (api.hip): M, Cholesky, xi = W L^{-H}.
+// real: the orbital blocks hold real values viewed as N_g / 2 complex numbers
+// (g.ng halved, ld halved); the small matrices then keep only their real part.
 template <typename T>
 ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
                          const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
-                         cx<double>* L_out, int* info_dev, bool mixed);
+                         cx<double>* L_out, int* info_dev, bool mixed, bool real = false);
 
 // Dense stages (dense.hip).  Small matrices are complex128, column-major.
-// C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]
+// C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]   (real_part: imaginary part
+// written as 0; for real data viewed as complex pairs the real part is the
+// real dot product)
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
-                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split);
+                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
+                   bool real_part = false);
 // Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K)
 template <typename T>
 ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
@@ -173,9 +184,10 @@ ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>
 // Fused: A = s (M + M^H)/2, A = L L^H, Lout = L (nullable), C = L^{-H}.
 // scratch: chol_scratch_elems(n) complex128 (used when n > 88).  info_dev gets
 // 0 or the first failing pivot; a nonzero *prior (nullable) is propagated.
+// real_only: A = s Re(M + M^T)/2 (the imaginary part of M is ignored).
 ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
                     cx<double>* C, cx<double>* scratch, int* info_dev,
-                    const int* prior = nullptr);
+                    const int* prior = nullptr, bool real_only = false);
 inline size_t chol_scratch_elems(int n) { return (size_t)n * n + (size_t)16 * n; }
 // *out = s * sum |A_ij|^2 over an m x n column-major block
 ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out);

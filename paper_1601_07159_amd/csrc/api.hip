@@ -1,6 +1,7 @@
 // C ABI of libace: argument validation, workspace, dispatch to the kernels.
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -137,7 +138,8 @@ static bool grid_supported(int n) {
 
 ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out) {
   if (!g) return fail(c, ACE_E_ARG, "grid is NULL");
-  if (prec != ACE_FP64 && prec != ACE_FP32 && prec != ACE_MIXED)
+  if (prec != ACE_FP64 && prec != ACE_FP32 && prec != ACE_MIXED && prec != ACE_REAL32 &&
+      prec != ACE_REAL64)
     return fail(c, ACE_E_ARG, "unknown precision");
   for (int a = 0; a < 3; ++a) {
     if (g->n[a] <= 0) return fail(c, ACE_E_ARG, "grid size must be positive");
@@ -161,7 +163,34 @@ ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out
   return ACE_OK;
 }
 
-size_t elem_bytes(ace_prec p) { return p == ACE_FP64 ? 16 : 8; }
+size_t elem_bytes(ace_prec p) {
+  switch (p) {
+    case ACE_FP64: return 16;
+    case ACE_REAL32: return 4;
+    case ACE_REAL64: return 8;
+    default: return 8;
+  }
+}
+
+static bool is_real(ace_prec p) { return p == ACE_REAL32 || p == ACE_REAL64; }
+
+// Real orbitals reuse the complex reduction/expansion kernels on N_g / 2
+// complex pairs (x0 + i x1, x2 + i x3, ...): the real part of a complex dot
+// product of two such views is the real dot product, and a real small matrix
+// maps pairs to pairs.  Needs an even ld and pair-aligned orbital starts.
+static ace_status check_real_view(ace_ctx c, const void* p, long ld, size_t eb,
+                                  const char* what) {
+  if (ld % 2 != 0 || ((uintptr_t)p % (2 * eb)) != 0)
+    return fail(c, ACE_E_ARG, std::string(what) +
+                                  ": real orbitals need an even ld and a start aligned to two values");
+  return ACE_OK;
+}
+
+static GridInfo half_view(const GridInfo& g) {
+  GridInfo h = g;
+  h.ng = g.ng / 2;  // every supported n is even
+  return h;
+}
 
 Span span_of(const void* p, int count, long ld, long ng, size_t eb) {
   const char* b = (const char*)p;
@@ -200,7 +229,7 @@ static ace_status finish_info(ace_ctx c, int* info_ws, int* info_dev) {
 template <typename T>
 ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
                          const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
-                         cx<double>* L_out, int* info_dev, bool mixed) {
+                         cx<double>* L_out, int* info_dev, bool mixed, bool real) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
   ACE_TRY(ws_begin(c, compress_ws_bytes(nb, g.ng)));
   ace_status st = ACE_OK;
@@ -210,47 +239,49 @@ ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ld
   int* info = (int*)ws_take(c, 256, &st);
   if (!M || !X || !C || !info) return st;
   // M = dV psi^H W, then -M made exactly Hermitian
-  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed));
+  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed, real));
   // -M made exactly Hermitian, -M = L L^H, C = L^{-H}
-  ACE_TRY(chol_inv(c, M, nb, -1.0, L_out, C, X, info));
+  ACE_TRY(chol_inv(c, M, nb, -1.0, L_out, C, X, info, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true));
   return finish_info(c, info, info_dev);
 }
 
 template ace_status compress_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, long,
                                          const cx<float>*, long, int, cx<float>*, long,
-                                         cx<double>*, int*, bool);
+                                         cx<double>*, int*, bool, bool);
 template ace_status compress_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, long,
                                           const cx<double>*, long, int, cx<double>*, long,
-                                          cx<double>*, int*, bool);
+                                          cx<double>*, int*, bool, bool);
 
 template <typename T>
 static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb, long ldxi,
-                          const cx<T>* X, int nx, long ldx, cx<T>* Y, long ldy) {
+                          const cx<T>* X, int nx, long ldx, cx<T>* Y, long ldy,
+                          bool real = false) {
   const size_t mat = align_up((size_t)nb * nx * sizeof(cx<double>), 256);
   ACE_TRY(ws_begin(c, mat + gemm_cn_scratch_bytes(nb, nx, g.ng)));
   ace_status st = ACE_OK;
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   if (!C) return st;
-  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, X, ldx, nx, g.ng, -g.dV, C, nb, false));
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, X, ldx, nx, g.ng, -g.dV, C, nb, false, real));
   return gemm_nn<T>(c, xi, ldxi, nb, C, nb, nx, Y, ldy, g.ng, false);
 }
 
 template <typename T>
 static ace_status energy_ace_t(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
-                               long ldphi, const cx<T>* xi, int nb, long ldxi, double* ex) {
+                               long ldphi, const cx<T>* xi, int nb, long ldxi, double* ex,
+                               bool real = false) {
   const size_t mat = align_up((size_t)nb * nocc * sizeof(cx<double>), 256);
   ACE_TRY(ws_begin(c, mat + gemm_cn_scratch_bytes(nb, nocc, g.ng)));
   ace_status st = ACE_OK;
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   if (!C) return st;
-  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, phi, ldphi, nocc, g.ng, g.dV, C, nb, false));
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, phi, ldphi, nocc, g.ng, g.dV, C, nb, false, real));
   return sumsq(c, C, (long)nb * nocc, -0.5, ex);
 }
 
 template <typename T>
 static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, long ldx, cx<T>* Q,
-                         long ldq, int* info_dev) {
+                         long ldq, int* info_dev, bool real = false) {
   const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
   const size_t tmp = align_up((size_t)n * g.ng * sizeof(cx<T>), 256);
   const size_t scr = align_up(chol_scratch_elems(n) * sizeof(cx<double>), 256);
@@ -264,12 +295,12 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   cx<T>* Y = (cx<T>*)ws_take(c, tmp, &st);
   if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
   // round 1: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
-  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false));
-  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1));
+  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false, real));
+  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true));
   // round 2 on Y restores orthogonality lost to rounding in round 1
-  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false));
-  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1));
+  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false, real));
+  ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1, real));
   ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true));
   return finish_info(c, info2, info_dev);
 }
@@ -398,6 +429,16 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   // calls, also under graph capture, need no allocation)
   const int nmax = std::max(max_nband, std::max(max_nx, max_nocc));
   const size_t mat = align_up((size_t)nmax * nmax * sizeof(cx<double>), 256);
+  if (is_real(prec)) {
+    const GridInfo gh = half_view(g);
+    size_t need = plan_build_real(c, g, 2 * eb, max_nocc, max_nband).bytes;
+    need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nocc).bytes);
+    need = std::max(need, compress_ws_bytes(max_nband, gh.ng));
+    need = std::max(need, orth_ws_bytes(nmax, gh.ng, 2 * eb));
+    need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), gh.ng));
+    need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, max_nocc, gh.ng));
+    return ws_begin(c, need);
+  }
   size_t need = std::max(plan_build(c, g, eb, max_nocc, max_nband, true).bytes,
                          plan_build(c, g, eb, max_nocc, max_nband, false).bytes);
   need = std::max(need, plan_build(c, g, eb, max_nocc, max_nocc, true).bytes);
@@ -424,6 +465,12 @@ ACE_EXPORT ace_status ace_build_W(ace_ctx c, const ace_grid* grid, ace_prec prec
   if (overlap(sw, span_of(phi, n_occ, ld_phi, g.ng, eb)) ||
       overlap(sw, span_of(psi, n_band, ld_psi, g.ng, eb)))
     return fail(c, ACE_E_ARG, "W overlaps an input");
+  if (prec == ACE_REAL64)
+    return build_W_real_impl<double>(c, g, (const double*)phi, n_occ, ld_phi, (const double*)psi,
+                                     n_band, ld_psi, (double*)W, ld_W, scale);
+  if (prec == ACE_REAL32)
+    return build_W_real_impl<float>(c, g, (const float*)phi, n_occ, ld_phi, (const float*)psi,
+                                    n_band, ld_psi, (float*)W, ld_W, scale);
   if (prec == ACE_FP64)
     return build_W_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi,
                                 (const cx<double>*)psi, n_band, ld_psi, (cx<double>*)W, ld_W,
@@ -447,6 +494,19 @@ ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec pre
   if (overlap(sx, span_of(psi, n_band, ld_psi, g.ng, eb)) ||
       overlap(sx, span_of(W, n_band, ld_W, g.ng, eb)))
     return fail(c, ACE_E_ARG, "xi overlaps an input");
+  if (is_real(prec)) {
+    ACE_TRY(check_real_view(c, psi, ld_psi, eb, "psi"));
+    ACE_TRY(check_real_view(c, W, ld_W, eb, "W"));
+    ACE_TRY(check_real_view(c, xi, ld_xi, eb, "xi"));
+    const GridInfo gh = half_view(g);
+    if (prec == ACE_REAL64)
+      return compress_impl<double>(c, gh, (const cx<double>*)psi, ld_psi / 2,
+                                   (const cx<double>*)W, ld_W / 2, n_band, (cx<double>*)xi,
+                                   ld_xi / 2, (cx<double>*)L_out, info_dev, false, true);
+    return compress_impl<float>(c, gh, (const cx<float>*)psi, ld_psi / 2, (const cx<float>*)W,
+                                ld_W / 2, n_band, (cx<float>*)xi, ld_xi / 2, (cx<double>*)L_out,
+                                info_dev, true, true);
+  }
   if (prec == ACE_FP64)
     return compress_impl<double>(c, g, (const cx<double>*)psi, ld_psi, (const cx<double>*)W, ld_W,
                               n_band, (cx<double>*)xi, ld_xi, (cx<double>*)L_out, info_dev, false);
@@ -469,6 +529,17 @@ ACE_EXPORT ace_status ace_apply(ace_ctx c, const ace_grid* grid, ace_prec prec, 
   if (overlap(sy, span_of(xi, n_band, ld_xi, g.ng, eb)) ||
       overlap(sy, span_of(X, n_x, ld_x, g.ng, eb)))
     return fail(c, ACE_E_ARG, "Y overlaps an input");
+  if (is_real(prec)) {
+    ACE_TRY(check_real_view(c, xi, ld_xi, eb, "xi"));
+    ACE_TRY(check_real_view(c, X, ld_x, eb, "X"));
+    ACE_TRY(check_real_view(c, Y, ld_y, eb, "Y"));
+    const GridInfo gh = half_view(g);
+    if (prec == ACE_REAL64)
+      return apply_t<double>(c, gh, (const cx<double>*)xi, n_band, ld_xi / 2,
+                             (const cx<double>*)X, n_x, ld_x / 2, (cx<double>*)Y, ld_y / 2, true);
+    return apply_t<float>(c, gh, (const cx<float>*)xi, n_band, ld_xi / 2, (const cx<float>*)X,
+                          n_x, ld_x / 2, (cx<float>*)Y, ld_y / 2, true);
+  }
   if (prec == ACE_FP64)
     return apply_t<double>(c, g, (const cx<double>*)xi, n_band, ld_xi, (const cx<double>*)X, n_x,
                            ld_x, (cx<double>*)Y, ld_y);
@@ -484,6 +555,20 @@ ACE_EXPORT ace_status ace_exchange_energy(ace_ctx c, const ace_grid* grid, ace_p
   ACE_TRY(check_grid(c, grid, prec, &g));
   ACE_TRY(check_block(c, phi, n_occ, ld_phi, g, "phi"));
   if (!ex_dev) return fail(c, ACE_E_ARG, "ex_dev is NULL");
+  if (xi && is_real(prec)) {
+    ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
+    const size_t eb = elem_bytes(prec);
+    ACE_TRY(check_real_view(c, phi, ld_phi, eb, "phi"));
+    ACE_TRY(check_real_view(c, xi, ld_xi, eb, "xi"));
+    const GridInfo gh = half_view(g);
+    if (prec == ACE_REAL64)
+      return energy_ace_t<double>(c, gh, (const cx<double>*)phi, n_occ, ld_phi / 2,
+                                  (const cx<double>*)xi, n_band, ld_xi / 2, ex_dev, true);
+    return energy_ace_t<float>(c, gh, (const cx<float>*)phi, n_occ, ld_phi / 2,
+                               (const cx<float>*)xi, n_band, ld_xi / 2, ex_dev, true);
+  }
+  if (is_real(prec))
+    return fail(c, ACE_E_UNSUPPORTED, "direct energy form for real orbitals (pass xi)");
   if (xi) {
     ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
     if (prec == ACE_FP64)
@@ -510,6 +595,12 @@ ACE_EXPORT ace_status ace_exchange_energy_grad(ace_ctx c, const ace_grid* grid, 
     return fail(c, ACE_E_ARG, "G overlaps phi");
   // G = 2 gbar dV V_X[phi] phi: the pair FFTs are recomputed (pairs i <= j)
   const double scale = 2.0 * g.dV;
+  if (prec == ACE_REAL64)
+    return build_W_real_impl<double>(c, g, (const double*)phi, n_occ, ld_phi, (const double*)phi,
+                                     n_occ, ld_phi, (double*)G, ld_G, scale, gbar_dev);
+  if (prec == ACE_REAL32)
+    return build_W_real_impl<float>(c, g, (const float*)phi, n_occ, ld_phi, (const float*)phi,
+                                    n_occ, ld_phi, (float*)G, ld_G, scale, gbar_dev);
   if (prec == ACE_FP64)
     return build_W_impl<double>(c, g, (const cx<double>*)phi, n_occ, ld_phi,
                                 (const cx<double>*)phi, n_occ, ld_phi, (cx<double>*)G, ld_G, scale,
@@ -530,6 +621,16 @@ ACE_EXPORT ace_status ace_orthonormalize(ace_ctx c, const ace_grid* grid, ace_pr
   const size_t eb = elem_bytes(prec);
   if (overlap(span_of(Q, n, ld_q, g.ng, eb), span_of(X, n, ld_x, g.ng, eb)))
     return fail(c, ACE_E_ARG, "Q overlaps X");
+  if (is_real(prec)) {
+    ACE_TRY(check_real_view(c, X, ld_x, eb, "X"));
+    ACE_TRY(check_real_view(c, Q, ld_q, eb, "Q"));
+    const GridInfo gh = half_view(g);
+    if (prec == ACE_REAL64)
+      return orth_t<double>(c, gh, (const cx<double>*)X, n, ld_x / 2, (cx<double>*)Q, ld_q / 2,
+                            info_dev, true);
+    return orth_t<float>(c, gh, (const cx<float>*)X, n, ld_x / 2, (cx<float>*)Q, ld_q / 2,
+                         info_dev, true);
+  }
   if (prec == ACE_FP64)
     return orth_t<double>(c, g, (const cx<double>*)X, n, ld_x, (cx<double>*)Q, ld_q, info_dev);
   return orth_t<float>(c, g, (const cx<float>*)X, n, ld_x, (cx<float>*)Q, ld_q, info_dev);

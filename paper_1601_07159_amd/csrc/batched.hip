@@ -81,6 +81,8 @@ ACE_EXPORT ace_status ace_build_batched(ace_ctx c, ace_prec prec, int n_inst,
   if (!c) return ACE_E_ARG;
   if (n_inst < 1 || !inst) return fail(c, ACE_E_ARG, "no instances");
   if (n_branches < 1 || n_branches > 16) return fail(c, ACE_E_ARG, "n_branches must be 1..16");
+  if (prec == ACE_REAL32 || prec == ACE_REAL64)
+    return fail(c, ACE_E_UNSUPPORTED, "batched builds take complex orbitals");
   const size_t eb = elem_bytes(prec);
   std::vector<Planned> plan(n_inst);
   for (int k = 0; k < n_inst; ++k) {

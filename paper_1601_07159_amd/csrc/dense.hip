@@ -44,7 +44,7 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
                                               cx<double>* A, int lda, cx<double>* T,
                                               cx<double>* __restrict__ Lout,
                                               cx<double>* __restrict__ C, int* __restrict__ info,
-                                              const int* __restrict__ prior) {
+                                              const int* __restrict__ prior, int real_only) {
   constexpr int NB = kCholNB;
   __shared__ int failed;
   const int t = threadIdx.x, nt = blockDim.x;
@@ -57,8 +57,10 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
   for (int j = wave; j < n; j += nw)
     for (int i = j + lane; i < n; i += 64) {
       const cx<double> a = M[i + (size_t)j * n], b = M[j + (size_t)i * n];
-      A[i + (size_t)j * lda] = (i == j) ? cx<double>{s * a.x, 0.0}
-                                        : cx<double>{0.5 * s * (a.x + b.x), 0.5 * s * (a.y - b.y)};
+      A[i + (size_t)j * lda] =
+          (i == j)    ? cx<double>{s * a.x, 0.0}
+          : real_only ? cx<double>{0.5 * s * (a.x + b.x), 0.0}
+                      : cx<double>{0.5 * s * (a.x + b.x), 0.5 * s * (a.y - b.y)};
     }
   __syncthreads();
 
@@ -286,7 +288,8 @@ __global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restr
                                                        double s, cx<double>* __restrict__ Lout,
                                                        cx<double>* __restrict__ C,
                                                        int* __restrict__ info,
-                                                       const int* __restrict__ prior) {
+                                                       const int* __restrict__ prior,
+                                                       int real_only) {
   __shared__ cx<double> colA[2][kCholRegMax];
   __shared__ cx<double> rowB[2][kCholRegMax];
   const int t = threadIdx.x, nt = blockDim.x;
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restr
 #pragma unroll
   for (int q = 0; q < kCholSlots; ++q) {
     a[q] = ai[q] == aj[q] ? cx<double>{s * m1[q].x, 0.0}
+           : real_only    ? cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.0}
                           : cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.5 * s * (m1[q].y - m2[q].y)};
     bv[q] = {0.0, 0.0};
     if (t + q * nt < tot_a && aj[q] == 0) colA[0][ai[q]] = a[q];
@@ -388,8 +392,9 @@ __global__ __launch_bounds__(1024) void k_chol_inv_global(const cx<double>* __re
                                                           cx<double>* __restrict__ Lout,
                                                           cx<double>* __restrict__ C,
                                                           int* __restrict__ info,
-                                                          const int* __restrict__ prior) {
-  chol_inv_body(M, n, s, A, n, A + (size_t)n * n, Lout, C, info, prior);
+                                                          const int* __restrict__ prior,
+                                                          int real_only) {
+  chol_inv_body(M, n, s, A, n, A + (size_t)n * n, Lout, C, info, prior, real_only);
 }
 
 __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A, long count,
@@ -409,16 +414,17 @@ __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A
 }  // namespace
 
 ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>* Lout,
-                    cx<double>* C, cx<double>* scratch, int* info_dev, const int* prior) {
+                    cx<double>* C, cx<double>* scratch, int* info_dev, const int* prior,
+                    bool real_only) {
   if (n <= kCholRegMax) {
     // enough threads for kCholSlots entries each, whole waves
     const int need = (n * (n + 1) / 2 + kCholSlots - 1) / kCholSlots;
     const int threads = need < 64 ? 64 : (need + 63) / 64 * 64;
     return launch(c, "chol_inv_reg", k_chol_inv_reg, dim3(1), dim3(threads), 0, M, n, s, Lout, C,
-                  info_dev, prior);
+                  info_dev, prior, real_only ? 1 : 0);
   }
   return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
-                Lout, C, info_dev, prior);
+                Lout, C, info_dev, prior, real_only ? 1 : 0);
 }
 
 ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out) {

@@ -406,6 +406,119 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
   }
 }
 
+// ---------------------------------------------------------------------------
+// Real orbitals (the paper's Gamma-point setting, Section 4): the pair charges
+// phi_a psi_j and phi_b psi_j of two occupied orbitals are real, so they are
+// transformed together as rho = phi_a psi_j + i phi_b psi_j.  The kernel K is
+// real and even, so the solve keeps real fields real:
+// u = ifftn(K fftn(rho)) = u_aj + i u_bj, and one complex transform serves
+// two pairs (the plane pass is shared with the complex path).
+// Unit p of a chunk: orbitals a = i0 + 2m, b = a + 1 (absent when 2m + 1 = A)
+// with m = p % Am, band j = j0 + p / Am.
+template <int N, typename T>
+__global__ __launch_bounds__(N) void k_pair_fwd_real_t1(const T* __restrict__ phi, long ldphi,
+                                                        const T* __restrict__ psi, long ldpsi,
+                                                        cx<T>* __restrict__ buf, int i0, int A,
+                                                        int Am, int j0, int nunits) {
+  constexpr int NN = N * N;
+  constexpr int LD = N + 1;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * nunits) return;
+  const int x0 = (int)(lid / nunits);
+  const int p = (int)(lid - (long)x0 * nunits);
+  const int m = p % Am, b = p / Am;
+  const int ia = i0 + 2 * m;
+  const bool has_b = 2 * m + 1 < A;
+  const T* fa = phi + (size_t)ia * ldphi + (size_t)x0 * NN;
+  const T* fb = has_b ? fa + ldphi : fa;
+  const T* ps = psi + (size_t)(j0 + b) * ldpsi + (size_t)x0 * NN;
+  const int t = threadIdx.x;
+  {
+    // issue every load of the slab before the first use
+    T va[N], vb[N], vy[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) va[r] = fa[r * N + t];
+#pragma unroll
+    for (int r = 0; r < N; ++r) vb[r] = fb[r * N + t];
+#pragma unroll
+    for (int r = 0; r < N; ++r) vy[r] = ps[r * N + t];
+    const T wb = has_b ? T(1) : T(0);
+#pragma unroll
+    for (int r = 0; r < N; ++r) s[r * LD + t] = cx<T>{va[r] * vy[r], wb * vb[r] * vy[r]};
+  }
+  __syncthreads();
+  cx<T> v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = s[t * LD + k];
+  fft_line<N, -1, T>(v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) s[t * LD + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = s[k * LD + t];
+  fft_line<N, -1, T>(v);
+  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k * N + t] = v[k];
+}
+
+// Accumulate pass for real orbitals: one thread per (x0, x2) pencil along
+// axis 1, one band per workgroup row; for each unit of the chunk, the inverse
+// FFT along axis 1 gives u_aj (real part) and u_bj (imaginary part), and
+// w_j += phi_a u_aj + phi_b u_bj in a thread-private LDS column.
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_pencil_accum_real(const T* __restrict__ phi, long ldphi,
+                                                          const cx<T>* __restrict__ buf,
+                                                          T* __restrict__ W, long ldW, int i0,
+                                                          int A, int Am, int j0, int nbc,
+                                                          int accumulate) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  __shared__ T acc[N * 64];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)TILES * nbc) return;
+  const int tile = (int)(lid / nbc);
+  const int b = (int)(lid - (long)tile * nbc);
+  const int t = threadIdx.x;
+  const int q = tile * 64 + t;
+  if (q >= NN) return;
+  const int x0 = q / N, x2 = q - x0 * N;
+  const size_t off = (size_t)x0 * NN + x2;
+#pragma unroll
+  for (int k = 0; k < N; ++k) acc[k * 64 + t] = T(0);
+  for (int m = 0; m < Am; ++m) {
+    const int ia = i0 + 2 * m;
+    const bool has_b = 2 * m + 1 < A;
+    const cx<T>* src = buf + ((size_t)m + (size_t)Am * b) * N * NN + off;
+    const T* pa = phi + (size_t)ia * ldphi + off;
+    const T* pb = has_b ? pa + ldphi : pa;
+    const T wb = has_b ? T(1) : T(0);
+    cx<T> v[N];
+    T fa[N], fb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = src[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) fa[k] = pa[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) fb[k] = pb[k * N];
+    fft_line<N, +1, T>(v);
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k * 64 + t] += fa[k] * v[k].x + wb * fb[k] * v[k].y;
+  }
+  T* w = W + (size_t)(j0 + b) * ldW + off;
+  if (accumulate) {
+    T old[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) old[k] = w[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k * N] = old[k] + acc[k * 64 + t];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k * N] = acc[k * 64 + t];
+  }
+}
+
 // Energy pencil pass: forward FFT along axis 0 and sum_G K |rho^(G)|^2 over 64
 // pencils per workgroup; one partial per workgroup, weighted 2 for i < j (the
 // pair j, i has the same sum because K(G) = K(-G)).
@@ -559,6 +672,29 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
   return pl;
 }
 
+// Real orbitals: units of two pairs; A orbitals (even unless all of them) x B
+// bands per chunk, Am = ceil(A / 2) units per band.
+BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband) {
+  BuildPlan pl;
+  const size_t unit_bytes = (size_t)g.ng * cx_bytes;
+  size_t budget = c->pair_budget;
+  long jblock = c->jblock;
+  if (!budget) budget = default_pair_budget();
+  long maxunits = (long)(budget / unit_bytes);
+  if (maxunits < 1) maxunits = 1;
+  int B = jblock > 0 ? (int)std::min<long>(nband, jblock) : nband;
+  B = (int)std::max<long>(1, std::min<long>(B, maxunits));
+  long am = std::max<long>(1, std::min<long>((nocc + 1) / 2, maxunits / B));
+  pl.B = B;
+  pl.A = (int)std::min<long>(nocc, 2 * am);
+  pl.sym = false;
+  pl.symblk = 0;
+  pl.pairs_alloc = (size_t)((pl.A + 1) / 2) * pl.B;
+  pl.bytes = align_up((size_t)g.ng * std::max<size_t>(cx_bytes / 2, 4), 256) +
+             align_up(pl.pairs_alloc * unit_bytes, 256);
+  return pl;
+}
+
 namespace {
 
 template <typename T>
@@ -702,6 +838,42 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
 }
 
 template <int N, typename T>
+ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, long ldphi,
+                          const T* psi, int nband, long ldpsi, T* W, long ldW, double scale,
+                          const double* dscale) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  const size_t unit_bytes = (size_t)g.ng * sizeof(cx<T>);
+  const BuildPlan pl = plan_build_real(c, g, sizeof(cx<T>), nocc, nband);
+  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
+  ace_status st;
+  if ((st = ws_begin(c, pl.bytes)) != ACE_OK) return st;
+  T* Kt = (T*)ws_take(c, kt_bytes, &st);
+  cx<T>* buf = (cx<T>*)ws_take(c, pl.pairs_alloc * unit_bytes, &st);
+  if (!Kt || !buf) return st;
+  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
+  const bool quad_p = use_quad<N, T>(c, true);
+  for (int j0 = 0; j0 < nband; j0 += pl.B) {
+    const int Bc = std::min(pl.B, nband - j0);
+    for (int i0 = 0; i0 < nocc; i0 += pl.A) {
+      const int Ac = std::min(pl.A, nocc - i0);
+      const int Am = (Ac + 1) / 2;
+      const int nu = Am * Bc;
+      if ((st = launch(c, "pair_fwd_real", k_pair_fwd_real_t1<N, T>,
+                       dim3(xcd_pad((long)N * nu)), dim3(N), 0, phi, ldphi, psi, ldpsi, buf, i0,
+                       Ac, Am, j0, nu)) != ACE_OK)
+        return st;
+      if ((st = plane<N, T>(c, quad_p, buf, Kt, nu)) != ACE_OK) return st;
+      if ((st = launch(c, "pencil_accum_real", k_pencil_accum_real<N, T>,
+                       dim3(xcd_pad((long)TILES * Bc)), dim3(64), 0, phi, ldphi,
+                       (const cx<T>*)buf, W, ldW, i0, Ac, Am, j0, Bc, i0 > 0 ? 1 : 0)) != ACE_OK)
+        return st;
+    }
+  }
+  return ACE_OK;
+}
+
+template <int N, typename T>
 ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                            double* ex_dev) {
   constexpr int NN = N * N;
@@ -766,6 +938,27 @@ ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, in
   }
 }
 
+template <typename T>
+ace_status build_W_real_impl(ace_ctx c, const GridInfo& g, const T* phi, int nocc, long ldphi,
+                             const T* psi, int nband, long ldpsi, T* W, long ldW, double scale,
+                             const double* dscale) {
+  switch (g.n) {
+#define ACE_CASE(NV) \
+  case NV:           \
+    return build_W_real_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale, dscale);
+    ACE_FOR_EACH_N(ACE_CASE)
+#undef ACE_CASE
+    default:
+      return fail(c, ACE_E_UNSUPPORTED, "grid size not compiled into the library");
+  }
+}
+
+template ace_status build_W_real_impl<float>(ace_ctx, const GridInfo&, const float*, int, long,
+                                             const float*, int, long, float*, long, double,
+                                             const double*);
+template ace_status build_W_real_impl<double>(ace_ctx, const GridInfo&, const double*, int, long,
+                                              const double*, int, long, double*, long, double,
+                                              const double*);
 template ace_status build_W_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int, long,
                                         const cx<float>*, int, long, cx<float>*, long, double,
                                         const double*);

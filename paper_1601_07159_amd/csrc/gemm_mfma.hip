@@ -303,7 +303,8 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
 template <typename P>
 __global__ __launch_bounds__(1024) void k_reduce_partials2(const cx<P>* __restrict__ partial,
                                                            int ks, int na, int nb, double alpha,
-                                                           cx<double>* __restrict__ C, int ldc) {
+                                                           cx<double>* __restrict__ C, int ldc,
+                                                           int real_part) {
   __shared__ double red[2][16][64];
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + el;
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_reduce_partials2(const cx<P>* __restri
   }
   if (g == 0 && idx < na * nb) {
     const int a = idx % na, b = idx / na;
-    C[a + (size_t)b * ldc] = {alpha * red[0][0][el], alpha * red[1][0][el]};
+    C[a + (size_t)b * ldc] = {alpha * red[0][0][el], real_part ? 0.0 : alpha * red[1][0][el]};
   }
 }
 
@@ -569,7 +570,8 @@ size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
 
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
-                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split) {
+                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
+                   bool real_part) {
   const CnShape s = sizeof(T) == 8 ? cn_shape(na, nb, K, 8, 12)
                     : bf16_split    ? cn_shape(na, nb, K, 12, 12)
                                     : cn_shape(na, nb, K, 16, 16);
@@ -593,7 +595,8 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
       return st;
   }
   return launch(c, "reduce_partials", k_reduce_partials2<T>, dim3((na * nb + 63) / 64),
-                dim3(1024), 0, (const cx<T>*)partial, (int)s.ks, na, nb, alpha, C, ldc);
+                dim3(1024), 0, (const cx<T>*)partial, (int)s.ks, na, nb, alpha, C, ldc,
+                real_part ? 1 : 0);
 }
 
 template <typename TIn, typename TAcc>
@@ -639,9 +642,9 @@ ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>
 }
 
 template ace_status gemm_cn<float>(ace_ctx, const cx<float>*, long, int, const cx<float>*, long,
-                                   int, long, double, cx<double>*, int, bool);
+                                   int, long, double, cx<double>*, int, bool, bool);
 template ace_status gemm_cn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, long,
-                                    int, long, double, cx<double>*, int, bool);
+                                    int, long, double, cx<double>*, int, bool, bool);
 template ace_status gemm_nn<float>(ace_ctx, const cx<float>*, long, int, const cx<double>*, int,
                                    int, cx<float>*, long, long, bool);
 template ace_status gemm_nn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, int,

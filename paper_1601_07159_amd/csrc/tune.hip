@@ -48,6 +48,8 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
   GridInfo g;
   ACE_TRY(check_grid(c, grid, prec, &g));
   if (n_occ < 1 || n_band < n_occ) return fail(c, ACE_E_ARG, "need 1 <= n_occ <= n_band");
+  if (prec == ACE_REAL32 || prec == ACE_REAL64)
+    return fail(c, ACE_E_UNSUPPORTED, "the tuner times the complex build");
   const size_t eb = elem_bytes(prec);
   void* psi = nullptr;
   void* W = nullptr;

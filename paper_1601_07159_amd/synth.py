@@ -92,6 +92,21 @@ def smooth_orbitals(n, L, nband: int, seed: int, ecut: float = 10.0,
     return np.ascontiguousarray(psi)
 
 
+def real_orbitals(n, L, nband: int, seed: int, ecut: float = 10.0) -> np.ndarray:
+    """Real smooth orbitals (the Gamma-point case), float64, shape (nband, n0,
+    n1, n2): the real parts of ``smooth_orbitals(n, L, nband, seed, ecut,
+    orthonormal=False)``, orthonormalised on the grid (QR with positive
+    diagonal of the N_g x nband matrix, then scaled so dV sum psi^2 = 1)."""
+    n3 = _as3(n, int)
+    L3 = _as3(L, float)
+    ng = n3[0] * n3[1] * n3[2]
+    dv = L3[0] * L3[1] * L3[2] / ng
+    x = np.real(smooth_orbitals(n, L, nband, seed, ecut, orthonormal=False))
+    q, r = np.linalg.qr(x.reshape(nband, ng).T)
+    q = q * np.sign(np.diag(r))[None, :]
+    return np.ascontiguousarray((q.T / np.sqrt(dv)).reshape((nband,) + n3))
+
+
 def planewave_orbitals(n, L, mvecs) -> np.ndarray:
     """Plane waves exp(i k.r)/sqrt(Omega), k = 2*pi*m/L, one per integer
     triple in ``mvecs``; complex128, shape (len(mvecs), n0, n1, n2)."""

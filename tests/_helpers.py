@@ -14,7 +14,10 @@ def rel(a, b) -> float:
 
 def to_gpu(x, prec):
     import torch
-    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    dt = {"fp64": torch.complex128, "real64": torch.float64,
+          "real32": torch.float32}.get(prec, torch.complex64)
+    if prec.startswith("real"):
+        x = np.real(x)
     return torch.from_numpy(np.ascontiguousarray(x)).to("cuda", dt)
 
 
@@ -33,4 +36,4 @@ def ggrid(n, L, kind="coulomb", mu=0.0, g0=0.0):
 
 
 def tol(prec):
-    return TOL_FP64 if prec == "fp64" else TOL_FP32
+    return TOL_FP64 if prec in ("fp64", "real64") else TOL_FP32

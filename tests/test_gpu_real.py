@@ -1,0 +1,118 @@
+"""GPU parity of the real-orbital (Gamma-point, Section 4) path against the
+FP64 oracle, through the C ABI: the build with two pair charges per complex
+FFT, and compress / apply / energy / orthonormalise on real arrays."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1601_07159_amd import synth
+from tests._helpers import ggrid, ogrid, rel, to_gpu, tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ace():
+    from paper_1601_07159_amd import ace as A
+    return A
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["real64", "real32"])
+@pytest.mark.parametrize("n,L,nocc,nband,kind,mu", [
+    (8, 4.0, 3, 5, "coulomb", 0.0),        # odd n_occ: one unit carries a single pair
+    (12, 5.0, 4, 7, "erfc", 0.6),
+    (16, 6.5, 6, 6, "coulomb", 0.0),
+    (24, 10.0, 7, 11, "coulomb", 0.0),
+    (32, 13.0, 5, 8, "erfc", 0.106),
+    (40, 17.0, 2, 3, "coulomb", 0.0),
+    (48, 20.5, 3, 4, "coulomb", 0.0),
+    (64, 27.0, 2, 3, "erfc", 0.3),
+    (72, 30.8, 3, 3, "coulomb", 0.0),
+])
+def test_build_W_real_matches_oracle(ace, prec, n, L, nocc, nband, kind, mu):
+    print(f"real build prec={prec} n={n} nocc={nocc} nband={nband}", flush=True)
+    psi = synth.real_orbitals(n, L, nband, seed=5 * n + nband)
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L, kind, mu))
+    assert np.abs(ref.imag).max() <= 1e-12 * np.abs(ref).max()
+    x = to_gpu(psi, prec)
+    W = ace.build_W(x[:nocc], x, ggrid(n, L, kind, mu), prec)
+    assert W.dtype == x.dtype
+    assert rel(_np(W), ref.real) <= tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["real64", "real32"])
+def test_build_W_real_chunked(ace, prec):
+    # a pair budget of 3 units forces blocks of 2 orbitals (one unit each) and
+    # accumulation across them, with an odd n_occ
+    n, L, nocc, nband = 16, 6.0, 7, 9
+    psi = synth.real_orbitals(n, L, nband, seed=8)
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L), scale=0.25)
+    ctx = ace.Context()
+    ctx.set_pair_budget(3 * n ** 3 * (16 if prec == "real64" else 8))
+    x = to_gpu(psi, prec)
+    W = ctx.build_W(x[:nocc], x, ggrid(n, L), prec, scale=0.25)
+    W2 = ctx.build_W(x[:nocc], x, ggrid(n, L), prec, scale=0.25)
+    ctx.close()
+    assert rel(_np(W), ref.real) <= tol(prec)
+    assert np.array_equal(_np(W), _np(W2))
+
+
+@pytest.mark.parametrize("prec", ["real64", "real32"])
+def test_real_compress_apply_energy(ace, prec):
+    import torch
+    n, L, nocc, nband = 24, 10.0, 6, 10
+    og, gg = ogrid(n, L), ggrid(n, L)
+    psi = synth.real_orbitals(n, L, nband, seed=21)
+    W = O.build_W(psi[:nocc], psi, og)
+    M, Lc, xi = O.compress(psi, W, og)
+    X = synth.real_orbitals(n, L, 4, seed=22)
+    Y = O.ace_apply(xi, X, og)
+    E = O.exchange_energy_ace(psi[:nocc], xi, og)
+    x = to_gpu(psi, prec)
+    Wg = to_gpu(W, prec)
+    info = torch.full((1,), -3, dtype=torch.int32, device="cuda")
+    xig, Lg = ace.compress(x, Wg, gg, prec, want_L=True, info=info)
+    Yg = ace.apply(xig, to_gpu(X, prec), gg, prec)
+    Eg = ace.exchange_energy(x[:nocc], gg, prec, xi=xig)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Ln = Lg.cpu().numpy()
+    assert np.abs(Ln.imag).max() == 0.0
+    assert rel(Ln.real, Lc.real) <= tol(prec)
+    assert rel(_np(xig), xi.real) <= tol(prec)
+    assert rel(_np(Yg), Y.real) <= tol(prec)
+    assert abs(float(Eg) - E) / abs(E) <= tol(prec)
+    # V_ACE psi = W on span(psi)
+    assert rel(_np(ace.apply(xig, x, gg, prec)), W.real) <= tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["real64", "real32"])
+def test_real_orthonormalize_and_gradient(ace, prec):
+    n, L = 16, 7.0
+    og, gg = ogrid(n, L), ggrid(n, L)
+    X = np.real(synth.smooth_orbitals(n, L, 6, seed=31, orthonormal=False))
+    Q = ace.orthonormalize(to_gpu(X, prec), gg, prec)
+    assert rel(_np(Q), O.orthonormalize(X, og).real) <= (1e-10 if prec == "real64" else 2e-5)
+    phi = synth.real_orbitals(n, L, 5, seed=32)
+    G = ace.exchange_energy_grad(to_gpu(phi, prec), gg, prec)
+    ref = 2.0 * O.exchange_energy_grad(phi, og)
+    assert rel(_np(G), ref.real) <= tol(prec)
+
+
+def test_real_rejects(ace):
+    import torch
+    n = 16
+    gg = ggrid(n, 6.0)
+    x = torch.zeros((3, n ** 3 + 1), dtype=torch.float64, device="cuda")
+    v = x[:, :n ** 3]                       # ld = N_g + 1 is odd
+    with pytest.raises(ace.AceError) as e:
+        ace.compress(v, v.clone(), gg, "real64")
+    assert e.value.status == 1
+    y = torch.zeros((3, n ** 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(ace.AceError) as e:
+        ace.exchange_energy(y, gg, "real64")  # direct form: complex only
+    assert e.value.status == 5
