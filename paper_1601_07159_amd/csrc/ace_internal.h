@@ -98,6 +98,7 @@ struct BuildPlan {
   int A, B;       // rectangle chunks: A orbitals x B bands
   bool sym;       // i <-> j symmetry on the occupied block
   int symblk;     // 0: the whole occupied triangle is one chunk; else block size
+  bool merged;    // triangle and the extra bands' rectangle form one chunk
   size_t pairs_alloc;
   size_t bytes;
 };

@@ -76,8 +76,20 @@ inline unsigned xcd_pad(long count) { return (unsigned)((count + kXcds - 1) / kX
 //  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
 //  mode 1: upper triangle i <= j of a diagonal block starting at i0 (= j0),
 //          block triangle index p0 + p (row-major in j)
+//  mode 3: the whole occupied triangle (A = n_occ orbitals, A(A+1)/2 pairs)
+//          followed by the rectangle of orbitals x bands j0 = A ... in one chunk
 __device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0, long p, int* i,
                                         int* j) {
+  if (mode == 3) {
+    const long tri = (long)A * (A + 1) / 2;
+    if (p >= tri) {
+      *i = (int)((p - tri) % A);
+      *j = j0 + (int)((p - tri) / A);
+      return;
+    }
+    mode = 1;  // triangle of the occupied block, which starts at orbital i0
+    j0 = i0;
+  }
   if (mode == 0) {
     *i = i0 + (int)(p % A);
     *j = j0 + (int)(p / A);
@@ -338,7 +350,10 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
 //  mode 1: the triangle chunk of a diagonal block (i0 = j0): pairs i <= j at
 //          local index j'(j'+1)/2 + i', and u_ij = conj(u_ji) for i > j;
 //  mode 2: a rectangle chunk stored the other way round, (j, i) at index
-//          b + nbc a, read conjugated (u_ij = conj(u_ji)).
+//          b + nbc a, read conjugated (u_ij = conj(u_ji));
+//  mode 3: the single chunk of pair_of's mode 3 (i0 = j0 = 0, A = n_occ):
+//          bands j < A as mode 1, bands j >= A from the rectangle after the
+//          triangle.
 template <int N, typename T>
 __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ phi, long ldphi,
                                                      const cx<T>* __restrict__ buf,
@@ -369,10 +384,13 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
     if (mode == 0) {
       pidx = (size_t)a + (size_t)A * b;
       conj_u = false;
-    } else if (mode == 1) {
+    } else if (mode == 1 || (mode == 3 && b < A)) {
       const int il = a, jl = b;  // local indices in the diagonal block
       pidx = il <= jl ? (size_t)jl * (jl + 1) / 2 + il : (size_t)il * (il + 1) / 2 + jl;
       conj_u = il > jl;
+    } else if (mode == 3) {
+      pidx = (size_t)A * (A + 1) / 2 + (size_t)a + (size_t)A * (b - A);
+      conj_u = false;
     } else {
       pidx = (size_t)b + (size_t)nbc * a;
       conj_u = true;
@@ -593,7 +611,7 @@ __global__ __launch_bounds__(1024) void k_sum_scaled(const double* __restrict__ 
   if (threadIdx.x == 0) *out = s * red[0];
 }
 
-size_t default_pair_budget() { return (size_t)2 << 30; }
+size_t default_pair_budget() { return (size_t)4 << 30; }
 
 }  // namespace
 
@@ -643,8 +661,15 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
   pl.sym = c->use_symmetry && psi_starts_with_phi && nocc >= 2;
   pl.symblk = 0;
   long sym_alloc = 0;
+  pl.merged = false;
   if (pl.sym) {
-    if (tri <= maxpairs && (long)g.n * tri < (1L << 31)) {
+    const long all = tri + (long)nocc * (nband - nocc);
+    if (all <= maxpairs && (long)g.n * all < (1L << 31)) {
+      // triangle and rectangle of the extra bands in flight together: one
+      // launch per pass for the whole build
+      pl.merged = true;
+      sym_alloc = all;
+    } else if (tri <= maxpairs && (long)g.n * tri < (1L << 31)) {
       sym_alloc = tri;
     } else {
       long bmax = (long)std::sqrt((double)maxpairs);
@@ -689,6 +714,7 @@ BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int noc
   pl.A = (int)std::min<long>(nocc, 2 * am);
   pl.sym = false;
   pl.symblk = 0;
+  pl.merged = false;
   pl.pairs_alloc = (size_t)((pl.A + 1) / 2) * pl.B;
   pl.bytes = align_up((size_t)g.ng * std::max<size_t>(cx_bytes / 2, 4), 256) +
              align_up(pl.pairs_alloc * unit_bytes, 256);
@@ -763,6 +789,15 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   const bool quad = use_quad<N, T>(c, false), quad_p = use_quad<N, T>(c, true);
   int jstart = 0;
   const dim3 pgrid_occ(xcd_pad((long)TILES * nocc));
+  if (pl.merged) {
+    const long all = (long)nocc * (nocc + 1) / 2 + (long)nocc * (nband - nocc);
+    if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 3, 0, nocc, nocc, 0L,
+                             (int)all)) != ACE_OK)
+      return st;
+    if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)all)) != ACE_OK) return st;
+    return launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nband)),
+                  dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, 0, nocc, 0, nband, 0, 3);
+  }
   if (sym && pl.symblk == 0) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
     // accumulates all i from it (u_ij = conj(u_ji))
