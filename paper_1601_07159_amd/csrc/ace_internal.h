@@ -178,10 +178,12 @@ template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
                    bool real_part = false);
-// Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K)
+// Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K); c_upper: C is upper
+// triangular and its zero blocks are skipped
 template <typename T>
 ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
-                   int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate);
+                   int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate,
+                   bool c_upper = false);
 // Fused: A = s (M + M^H)/2, A = L L^H, Lout = L (nullable), C = L^{-H}.
 // scratch: chol_scratch_elems(n) complex128 (used when n > 88).  info_dev gets
 // 0 or the first failing pivot; a nonzero *prior (nullable) is propagated.

@@ -437,11 +437,15 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
 // The grid-row loads run R steps (4 orbitals each) ahead of the MFMAs.
 constexpr int kNnResA = 80;
 
+// upper: C is upper triangular (C[a][b] = 0 for a > b), so a step of four
+// orbitals past the last column of a 16-column block adds nothing to it and
+// its MFMAs are skipped (the triangular products xi = W L^{-H} and the
+// orthonormalisation's X R^{-1} do about 60% of the full work).
 template <typename TIn, typename TAcc, int NBB>
 __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__ A, long lda,
                                                      int na, const cx<double>* __restrict__ C,
                                                      int ldc, int nb, cx<TIn>* __restrict__ Y,
-                                                     long ldy, long K) {
+                                                     long ldy, long K, int upper) {
   typedef typename Acc4<TAcc>::type acc_t;
   constexpr int XB = NnShape<TAcc>::XB;
   constexpr int NBC = 16 * NBB;
@@ -498,6 +502,7 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
         if (st < nsteps) {
 #pragma unroll
           for (int y = 0; y < NBB; ++y) {
+            if (upper && 4 * st > b0 + 16 * y + 15) continue;  // wave-uniform
             const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
             const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
 #pragma unroll
@@ -602,7 +607,7 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
 template <typename TIn, typename TAcc>
 static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, long lda, int na,
                               const cx<double>* C, int ldc, int nb, cx<TIn>* Y, long ldy,
-                              long K) {
+                              long K, bool c_upper) {
   const int nbb = nb <= 16 ? 1 : nb <= 32 ? 2 : nb <= 48 ? 3 : nb <= 80 && nb > 64 ? 5 : 4;
   const dim3 block(256);
   const bool resident = na <= kNnResA;
@@ -615,7 +620,7 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
       const long cap = (256 + gy - 1) / gy;                                                    \
       if (gx > cap) gx = cap;                                                                  \
       return launch(c, name, k_nn_mfma_res<TIn, TAcc, NBBV>, dim3((unsigned)gx, gy), dim3(512), \
-                    0, A, lda, na, C, ldc, nb, Y, ldy, K);                                     \
+                    0, A, lda, na, C, ldc, nb, Y, ldy, K, c_upper ? 1 : 0);                    \
     }                                                                                          \
     const long rows = NnShape<TAcc>::ROWS;                                                    \
     const dim3 grid((unsigned)((K + rows - 1) / rows), gy);                                    \
@@ -635,10 +640,10 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
 
 template <typename T>
 ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>* C, int ldc,
-                   int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate) {
+                   int nb, cx<T>* Y, long ldy, long K, bool fp64_accumulate, bool c_upper) {
   if (fp64_accumulate || std::is_same<T, double>::value)
-    return nn_dispatch<T, double>(c, "nn_mfma_f64", A, lda, na, C, ldc, nb, Y, ldy, K);
-  return nn_dispatch<T, float>(c, "nn_mfma_f32", A, lda, na, C, ldc, nb, Y, ldy, K);
+    return nn_dispatch<T, double>(c, "nn_mfma_f64", A, lda, na, C, ldc, nb, Y, ldy, K, c_upper);
+  return nn_dispatch<T, float>(c, "nn_mfma_f32", A, lda, na, C, ldc, nb, Y, ldy, K, c_upper);
 }
 
 template ace_status gemm_cn<float>(ace_ctx, const cx<float>*, long, int, const cx<float>*, long,
@@ -646,8 +651,8 @@ template ace_status gemm_cn<float>(ace_ctx, const cx<float>*, long, int, const c
 template ace_status gemm_cn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, long,
                                     int, long, double, cx<double>*, int, bool, bool);
 template ace_status gemm_nn<float>(ace_ctx, const cx<float>*, long, int, const cx<double>*, int,
-                                   int, cx<float>*, long, long, bool);
+                                   int, cx<float>*, long, long, bool, bool);
 template ace_status gemm_nn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, int,
-                                    int, cx<double>*, long, long, bool);
+                                    int, cx<double>*, long, long, bool, bool);
 
 }  // namespace ace
