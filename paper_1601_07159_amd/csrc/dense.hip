@@ -223,25 +223,23 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
 }
 
 // ---------------------------------------------------------------------------
-// Fused factorisation for n <= kCholRegMax, one workgroup, matrix entries in
-// registers.  Every thread owns up to kCholSlots entries of the lower triangle
-// of A (the Cholesky side) and up to kCholSlots strictly-lower entries of
-// B (the inverse side) for the whole kernel; one barrier per column k.
-//   Cholesky  right-looking on the unscaled Schur complement:
-//             a_ij -= a_ik conj(a_jk) / a_kk  for i >= j > k,
-//             L_ik = a_ik / sqrt(a_kk).
-//   inverse   X = L^{-1} row by row in the same sweep: X_kj = B_kj / L_kk with
-//             B_kj = delta_kj - sum_{m<k} L_km X_mj, accumulated right-looking
-//             (B_ij -= L_ik X_kj for i > k >= j).
-// Column k of the Schur complement and row k of B become final during step
-// k - 1; their owners publish them to LDS (two buffers, alternating with the
-// parity of k), and after the barrier every thread reads what it needs for
-// step k.  A slot reads its LDS operands only while active (the LDS traffic of
-// reading every slot at every step would dominate), but the reads of all
-// slots are issued before the first is used.  The Cholesky entries are
-// numbered by column from the last one backwards, so the entries still active
-// at step k form a prefix and fill whole waves; within a wave the column
-// index is mostly uniform and its reads are broadcasts.
+// Factorisation for n <= kCholRegMax in two kernels.
+// k_chol_reg: one workgroup, the entries of the lower triangle of A owned by
+// threads in registers (up to kCholSlots each) for the whole kernel; one
+// barrier per column k.  Right-looking on the unscaled Schur complement:
+//   a_ij -= a_ik conj(a_jk) / a_kk  for i >= j > k,   L_ik = a_ik / sqrt(a_kk).
+// Column k + 1 becomes final during step k; its owners publish it to LDS (two
+// buffers, alternating with the parity of k), and after the barrier every
+// thread reads what it needs.  A slot reads LDS only while active (the
+// traffic of reading every slot at every step would dominate), but the reads
+// of all slots are issued before the first is used.  The entries are numbered
+// by column from the last one backwards, so the entries still active at step
+// k form a prefix and fill whole waves; within a wave the column index is
+// mostly uniform and its reads are broadcasts.
+// k_tri_inv: C = L^{-H}, one wave per column of L^{-1} (forward substitution,
+// many workgroups in parallel).  The fused single-workgroup form that also
+// carried the inverse in the Cholesky sweep measured 101 us at n = 80, the
+// two kernels 62 + 23 us.
 constexpr int kCholRegMax = 88;
 constexpr int kCholSlots = 4;  // ceil(88 * 89 / 2 / 1024)
 
@@ -255,18 +253,6 @@ __device__ __forceinline__ void tri_index_desc(int e, int n, int* i, int* j) {
   }
   *j = jj;
   *i = jj + e;
-}
-
-__device__ __forceinline__ void tri_index_strict(int e, int n, int* i, int* j) {
-  // e-th entry of the strict lower triangle, columns 0, 1, ...
-  int jj = 0, len = n - 1;
-  while (e >= len) {
-    e -= len;
-    ++jj;
-    --len;
-  }
-  *j = jj;
-  *i = jj + 1 + e;
 }
 
 // 1/sqrt(d) from the hardware estimate, refined by three Newton-Raphson steps
@@ -284,33 +270,28 @@ __device__ __forceinline__ void pivot_terms(double d, double* invr, double* invd
   *r = d * y;
 }
 
-__global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restrict__ M, int n,
-                                                       double s, cx<double>* __restrict__ Lout,
-                                                       cx<double>* __restrict__ C,
-                                                       int* __restrict__ info,
-                                                       const int* __restrict__ prior,
-                                                       int real_only) {
+// Cholesky only (the inverse follows in k_tri_inv): the Cholesky side of the
+// fused register kernel; column k of L goes to Lw (and Lout) as it is final.
+__global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict__ M, int n,
+                                                   double s, cx<double>* __restrict__ Lw,
+                                                   cx<double>* __restrict__ Lout,
+                                                   int* __restrict__ info,
+                                                   const int* __restrict__ prior, int real_only) {
   __shared__ cx<double> colA[2][kCholRegMax];
-  __shared__ cx<double> rowB[2][kCholRegMax];
   const int t = threadIdx.x, nt = blockDim.x;
   if (prior && *prior != 0) {
     if (t == 0) *info = *prior;
     return;
   }
-  const int tot_a = n * (n + 1) / 2, tot_b = n * (n - 1) / 2;
-  // owned entries; an unused slot gets indices that no step activates
-  int ai[kCholSlots], aj[kCholSlots], bi[kCholSlots], bj[kCholSlots];
-  cx<double> a[kCholSlots], bv[kCholSlots];
+  const int tot_a = n * (n + 1) / 2;
+  int ai[kCholSlots], aj[kCholSlots];
+  cx<double> a[kCholSlots];
 #pragma unroll
   for (int q = 0; q < kCholSlots; ++q) {
     const int e = t + q * nt;
     ai[q] = aj[q] = 0;  // column 0 is never updated
-    bi[q] = 0;          // i > k never holds
-    bj[q] = n;
     if (e < tot_a) tri_index_desc(e, n, &ai[q], &aj[q]);
-    if (e < tot_b) tri_index_strict(e, n, &bi[q], &bj[q]);
   }
-  // A = s (M + M^H) / 2 on the owned entries; all loads issued together
   cx<double> m1[kCholSlots], m2[kCholSlots];
 #pragma unroll
   for (int q = 0; q < kCholSlots; ++q) {
@@ -325,7 +306,6 @@ __global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restr
     a[q] = ai[q] == aj[q] ? cx<double>{s * m1[q].x, 0.0}
            : real_only    ? cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.0}
                           : cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.5 * s * (m1[q].y - m2[q].y)};
-    bv[q] = {0.0, 0.0};
     if (t + q * nt < tot_a && aj[q] == 0) colA[0][ai[q]] = a[q];
   }
   __syncthreads();
@@ -333,36 +313,27 @@ __global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restr
   for (int k = 0; k < n; ++k) {
     const int p = k & 1;
     const double d = colA[p][k].x;
-    // operands of the active slots, all issued before the first use
-    cx<double> ci[kCholSlots], cj[kCholSlots], li[kCholSlots], xk[kCholSlots];
+    cx<double> ci[kCholSlots], cj[kCholSlots];
 #pragma unroll
-    for (int q = 0; q < kCholSlots; ++q) {
-      if (aj[q] > k) {  // i >= j > k
+    for (int q = 0; q < kCholSlots; ++q)
+      if (aj[q] > k) {
         ci[q] = colA[p][ai[q]];
         cj[q] = colA[p][aj[q]];
       }
-      if (bj[q] <= k && k < bi[q]) {  // i > k >= j
-        li[q] = colA[p][bi[q]];
-        xk[q] = rowB[p][bj[q]];
-      }
-    }
     cx<double> oc = {0.0, 0.0};
-    if (t < n) oc = t > k ? colA[p][t] : rowB[p][t];
-    if (!(d > 0.0) || !isfinite(d)) {  // the same value in every thread
+    if (t < n && t > k) oc = colA[p][t];
+    if (!(d > 0.0) || !isfinite(d)) {
       fail_k = k + 1;
       break;
     }
     double invr, invd, r;
     pivot_terms(d, &invr, &invd, &r);
-    // column k of L and of C = X^H (row k of X), zeros elsewhere
     if (t < n) {
-      if (Lout)
-        Lout[t + (size_t)k * n] = t < k    ? cx<double>{0.0, 0.0}
-                                  : t == k ? cx<double>{r, 0.0}
-                                           : cx<double>{oc.x * invr, oc.y * invr};
-      C[t + (size_t)k * n] = t > k    ? cx<double>{0.0, 0.0}
-                             : t == k ? cx<double>{invr, 0.0}
-                                      : cx<double>{oc.x * invr, -oc.y * invr};
+      const cx<double> l = t < k    ? cx<double>{0.0, 0.0}
+                           : t == k ? cx<double>{r, 0.0}
+                                    : cx<double>{oc.x * invr, oc.y * invr};
+      Lw[t + (size_t)k * n] = l;
+      if (Lout) Lout[t + (size_t)k * n] = l;
     }
 #pragma unroll
     for (int q = 0; q < kCholSlots; ++q)
@@ -372,19 +343,67 @@ __global__ __launch_bounds__(1024) void k_chol_inv_reg(const cx<double>* __restr
         a[q].y -= u.y * invd;
         if (aj[q] == k + 1) colA[p ^ 1][ai[q]] = a[q];
       }
-    // inverse side: L_ik X_kj = (a_ik / r) (B_kj / r), B_kk = 1
-#pragma unroll
-    for (int q = 0; q < kCholSlots; ++q)
-      if (bj[q] <= k && k < bi[q]) {
-        const cx<double> xr = bj[q] == k ? cx<double>{1.0, 0.0} : xk[q];
-        const cx<double> u = cmul_d(li[q], xr);
-        bv[q].x -= u.x * invd;
-        bv[q].y -= u.y * invd;
-        if (bi[q] == k + 1) rowB[p ^ 1][bj[q]] = bv[q];
-      }
     __syncthreads();
   }
   if (t == 0) *info = fail_k;
+}
+
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// C = L^{-H} for n <= kCholRegMax: one wave per column j of X = L^{-1}, the
+// lower triangle of L staged in LDS.  Column-oriented forward substitution:
+// lane i holds rows i and i + 64 of y = e_j - sum_{m<k} L_:m x_m; at step k
+// the owner of row k forms x_k = y_k / L_kk and broadcasts it, and every
+// lane subtracts L_ik x_k.  Row j of C is conj(x).
+__global__ __launch_bounds__(64) void k_tri_inv(const cx<double>* __restrict__ L, int n,
+                                                cx<double>* __restrict__ C,
+                                                const int* __restrict__ info) {
+  __shared__ cx<double> Ls[kCholRegMax * kCholRegMax];
+  if (*info != 0) return;
+  const int j = blockIdx.x, lane = threadIdx.x;
+  // columns j .. n-1 (zeros above the diagonal included), 32 loads in flight
+  const int nn = n * n;
+  for (int e0 = j * n; e0 < nn; e0 += 32 * 64) {
+    cx<double> v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = e0 + u * 64 + lane;
+      v[u] = e < nn ? L[e] : cx<double>{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = e0 + u * 64 + lane;
+      if (e < nn) Ls[e] = v[u];
+    }
+  }
+  __syncthreads();
+  const int i0 = lane, i1 = lane + 64;
+  cx<double> y0 = {i0 == j ? 1.0 : 0.0, 0.0}, y1 = {i1 == j ? 1.0 : 0.0, 0.0};
+  const double inv0 = (i0 >= j && i0 < n) ? 1.0 / Ls[i0 + (size_t)i0 * n].x : 0.0;
+  const double inv1 = (i1 >= j && i1 < n) ? 1.0 / Ls[i1 + (size_t)i1 * n].x : 0.0;
+  for (int k = lane; k < j; k += 64) C[j + (size_t)k * n] = {0.0, 0.0};
+  // rows beyond n and above k read zeros (the staged upper triangle is zero;
+  // rows >= n are clamped), so the update needs no branch
+  const int r0 = i0 < n ? i0 : n - 1, r1 = i1 < n ? i1 : n - 1;
+  for (int k = j; k < n; ++k) {
+    const cx<double> l0 = i0 > k ? Ls[r0 + k * n] : cx<double>{0.0, 0.0};
+    const cx<double> l1 = i1 > k && i1 < n ? Ls[r1 + k * n] : cx<double>{0.0, 0.0};
+    const cx<double> own = k < 64 ? cx<double>{y0.x * inv0, y0.y * inv0}
+                                  : cx<double>{y1.x * inv1, y1.y * inv1};
+    const int src = k & 63;  // the same in every lane: a scalar read of the owner's value
+    const cx<double> xk = {bcast_lane(own.x, src), bcast_lane(own.y, src)};
+    if (lane == src) C[j + (size_t)k * n] = {xk.x, -xk.y};
+    const cx<double> u0 = cmul_d(l0, xk), u1 = cmul_d(l1, xk);
+    y0.x -= u0.x;
+    y0.y -= u0.y;
+    y1.x -= u1.x;
+    y1.y -= u1.y;
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_chol_inv_global(const cx<double>* __restrict__ M, int n,
@@ -417,11 +436,13 @@ ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>*
                     cx<double>* C, cx<double>* scratch, int* info_dev, const int* prior,
                     bool real_only) {
   if (n <= kCholRegMax) {
-    // enough threads for kCholSlots entries each, whole waves
     const int need = (n * (n + 1) / 2 + kCholSlots - 1) / kCholSlots;
     const int threads = need < 64 ? 64 : (need + 63) / 64 * 64;
-    return launch(c, "chol_inv_reg", k_chol_inv_reg, dim3(1), dim3(threads), 0, M, n, s, Lout, C,
-                  info_dev, prior, real_only ? 1 : 0);
+    ace_status st = launch(c, "chol_reg", k_chol_reg, dim3(1), dim3(threads), 0, M, n, s,
+                           scratch, Lout, info_dev, prior, real_only ? 1 : 0);
+    if (st != ACE_OK) return st;
+    return launch(c, "tri_inv", k_tri_inv, dim3(n), dim3(64), 0, (const cx<double>*)scratch, n,
+                  C, (const int*)info_dev);
   }
   return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
                 Lout, C, info_dev, prior, real_only ? 1 : 0);
