@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "mixed", "real64", "real32"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--pair-budget", type=int, default=0,
+                    help="bytes of pair spectra in flight (0 = library default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -154,6 +156,8 @@ def main():
     psi_in = torch.from_numpy(psi_np).to(dev, cdt)
 
     ctx = ace.Context(0)
+    if args.pair_budget:
+        ctx.set_pair_budget(args.pair_budget)
     ctx.reserve(grid, prec, nocc, nband, nx)
 
     def make_bufs(dt):
