@@ -449,7 +449,11 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
   typedef typename Acc4<TAcc>::type acc_t;
   constexpr int XB = NnShape<TAcc>::XB;
   constexpr int NBC = 16 * NBB;
-  constexpr int R = 8;
+  constexpr int R = sizeof(TIn) == 8 ? 4 : 8;  // grid-row loads in flight
+  // With 3 or 4 column blocks the skip branches make the register allocator
+  // spill the accumulators (hundreds of spills); there the zero blocks of an
+  // upper-triangular C are multiplied instead.
+  constexpr bool kSkip = NBB != 3 && NBB != 4;
   __shared__ TAcc cs_re[kNnResA][NBC];
   __shared__ TAcc cs_im[kNnResA][NBC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -492,19 +496,31 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
         if (st < nsteps && a < na && r < K) v[x] = A[(size_t)a * lda + r];
       }
     };
+    // C entries of a step, read from LDS one step ahead of their use (the
+    // step past the last one re-reads the last: rows stay inside cs_*)
+    TAcc cb[2][NBB][2];
+    auto loadc = [&](TAcc (&cv)[NBB][2], int st) {
+      const int a = 4 * (st < nsteps ? st : nsteps - 1) + kq;
+#pragma unroll
+      for (int y = 0; y < NBB; ++y) {
+        cv[y][0] = cs_re[a][16 * y + r16];
+        cv[y][1] = cs_im[a][16 * y + r16];
+      }
+    };
 #pragma unroll
     for (int j = 0; j < R - 1; ++j) load(buf[j], j);
+    loadc(cb[0], 0);
     for (int st0 = 0; st0 < nsteps; st0 += R) {
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         load(buf[(j + R - 1) % R], st0 + j + R - 1);
-        const int st = st0 + j;
+        const int st = st0 + j;  // st0 is a multiple of R (even): step st uses cb[j & 1]
+        loadc(cb[(j + 1) & 1], st + 1);
         if (st < nsteps) {
 #pragma unroll
           for (int y = 0; y < NBB; ++y) {
-            if (upper && 4 * st > b0 + 16 * y + 15) continue;  // wave-uniform
-            const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
-            const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
+            if (kSkip && upper && 4 * st > b0 + 16 * y + 15) continue;  // wave-uniform
+            const TAcc cr = cb[j & 1][y][0], ci = cb[j & 1][y][1];
 #pragma unroll
             for (int x = 0; x < XB; ++x) {
               const TAcc xr = (TAcc)buf[j][x].x, xi = (TAcc)buf[j][x].y;
