@@ -72,6 +72,22 @@ __device__ __forceinline__ long xcd_logical(long bid, long padded) {
 }
 inline unsigned xcd_pad(long count) { return (unsigned)((count + kXcds - 1) / kXcds * kXcds); }
 
+
+// Streaming (non-temporal) store of one complex value.  The forward slab
+// pass writes every pair spectrum once and re-reads the orbital slabs from
+// L2; plain stores of the 2-3 GB stream evict those slabs (measured at
+// 48^3: 0.88 -> 0.68 ms for the pass with streaming stores).
+template <typename T>
+__device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(f2{v.x, v.y}, reinterpret_cast<f2*>(p));
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(d2{v.x, v.y}, reinterpret_cast<d2*>(p));
+  }
+}
+
 // Pair of block-local index p.
 //  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
 //  mode 1: upper triangle i <= j of a diagonal block starting at i0 (= j0),
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(N * P) void k_pair_fwd_slab_t1(const cx<T>* __restr
   if (!live) return;
   cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
 #pragma unroll
-  for (int k = 0; k < N; ++k) out[k * N + t] = v[k];
+  for (int k = 0; k < N; ++k) store_nt(&out[k * N + t], v[k]);
 }
 
 // Plane pass: one group of N threads per (k1 plane, pair).  The plane
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict
   fft_quad_d2b<N, -1, T>(v, h);
   cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
 #pragma unroll
-  for (int k = 0; k < M; ++k) out[quad_block_index(k, M, h) * N] = v[k];
+  for (int k = 0; k < M; ++k) store_nt(&out[quad_block_index(k, M, h) * N], v[k]);
 }
 
 // Plane pass: one workgroup per (k1 plane, pair).  Along axis 0 (column l of
@@ -478,7 +494,7 @@ __global__ __launch_bounds__(N) void k_pair_fwd_real_t1(const T* __restrict__ ph
   fft_line<N, -1, T>(v);
   cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
 #pragma unroll
-  for (int k = 0; k < N; ++k) out[k * N + t] = v[k];
+  for (int k = 0; k < N; ++k) store_nt(&out[k * N + t], v[k]);
 }
 
 // Accumulate pass for real orbitals: one thread per (x0, x2) pencil along
