@@ -270,14 +270,28 @@ __device__ __forceinline__ void pivot_terms(double d, double* invr, double* invd
   *r = d * y;
 }
 
-// Cholesky only (the inverse follows in k_tri_inv): the Cholesky side of the
-// fused register kernel; column k of L goes to Lw (and Lout) as it is final.
+// Pivot terms of d (1/sqrt(d), 1/d, sqrt(d)) and a failure flag, to LDS.
+__device__ __forceinline__ void publish_pivot(double d, double* pv) {
+  const bool ok = d > 0.0 && isfinite(d);
+  double invr = 0.0, invd = 0.0, r = 0.0;
+  if (ok) pivot_terms(d, &invr, &invd, &r);
+  pv[0] = invr;
+  pv[1] = invd;
+  pv[2] = r;
+  pv[3] = ok ? 0.0 : 1.0;
+}
+
+// Cholesky only (the inverse follows in k_tri_inv): column k of L goes to Lw
+// (and Lout) as it is final.  The owner of the next diagonal entry computes
+// its pivot terms right after its update and publishes them with the column,
+// so the other threads start each step with them.
 __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict__ M, int n,
                                                    double s, cx<double>* __restrict__ Lw,
                                                    cx<double>* __restrict__ Lout,
                                                    int* __restrict__ info,
                                                    const int* __restrict__ prior, int real_only) {
   __shared__ cx<double> colA[2][kCholRegMax];
+  __shared__ double piv[2][4];
   const int t = threadIdx.x, nt = blockDim.x;
   if (prior && *prior != 0) {
     if (t == 0) *info = *prior;
@@ -306,13 +320,16 @@ __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict_
     a[q] = ai[q] == aj[q] ? cx<double>{s * m1[q].x, 0.0}
            : real_only    ? cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.0}
                           : cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.5 * s * (m1[q].y - m2[q].y)};
-    if (t + q * nt < tot_a && aj[q] == 0) colA[0][ai[q]] = a[q];
+    if (t + q * nt < tot_a && aj[q] == 0) {
+      colA[0][ai[q]] = a[q];
+      if (ai[q] == 0) publish_pivot(a[q].x, piv[0]);
+    }
   }
   __syncthreads();
   int fail_k = 0;
   for (int k = 0; k < n; ++k) {
     const int p = k & 1;
-    const double d = colA[p][k].x;
+    const double invr = piv[p][0], invd = piv[p][1], r = piv[p][2], bad = piv[p][3];
     cx<double> ci[kCholSlots], cj[kCholSlots];
 #pragma unroll
     for (int q = 0; q < kCholSlots; ++q)
@@ -322,12 +339,10 @@ __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict_
       }
     cx<double> oc = {0.0, 0.0};
     if (t < n && t > k) oc = colA[p][t];
-    if (!(d > 0.0) || !isfinite(d)) {
+    if (bad != 0.0) {
       fail_k = k + 1;
       break;
     }
-    double invr, invd, r;
-    pivot_terms(d, &invr, &invd, &r);
     if (t < n) {
       const cx<double> l = t < k    ? cx<double>{0.0, 0.0}
                            : t == k ? cx<double>{r, 0.0}
@@ -341,7 +356,10 @@ __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict_
         const cx<double> u = cmulcj_d(ci[q], cj[q]);
         a[q].x -= u.x * invd;
         a[q].y -= u.y * invd;
-        if (aj[q] == k + 1) colA[p ^ 1][ai[q]] = a[q];
+        if (aj[q] == k + 1) {
+          colA[p ^ 1][ai[q]] = a[q];
+          if (ai[q] == k + 1) publish_pivot(a[q].x, piv[p ^ 1]);
+        }
       }
     __syncthreads();
   }
@@ -360,28 +378,31 @@ __device__ __forceinline__ double bcast_lane(double v, int src) {
 // lane i holds rows i and i + 64 of y = e_j - sum_{m<k} L_:m x_m; at step k
 // the owner of row k forms x_k = y_k / L_kk and broadcasts it, and every
 // lane subtracts L_ik x_k.  Row j of C is conj(x).
-__global__ __launch_bounds__(64) void k_tri_inv(const cx<double>* __restrict__ L, int n,
-                                                cx<double>* __restrict__ C,
-                                                const int* __restrict__ info) {
+__global__ __launch_bounds__(256) void k_tri_inv(const cx<double>* __restrict__ L, int n,
+                                                 cx<double>* __restrict__ C,
+                                                 const int* __restrict__ info) {
   __shared__ cx<double> Ls[kCholRegMax * kCholRegMax];
   if (*info != 0) return;
-  const int j = blockIdx.x, lane = threadIdx.x;
-  // columns j .. n-1 (zeros above the diagonal included), 32 loads in flight
+  const int j = blockIdx.x, t = threadIdx.x;
+  // columns j .. n-1 (zeros above the diagonal included), staged by all four
+  // waves with 32 loads in flight per lane; wave 0 alone then substitutes
   const int nn = n * n;
-  for (int e0 = j * n; e0 < nn; e0 += 32 * 64) {
+  for (int e0 = j * n; e0 < nn; e0 += 32 * 256) {
     cx<double> v[32];
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int e = e0 + u * 64 + lane;
+      const int e = e0 + u * 256 + t;
       v[u] = e < nn ? L[e] : cx<double>{0.0, 0.0};
     }
 #pragma unroll
     for (int u = 0; u < 32; ++u) {
-      const int e = e0 + u * 64 + lane;
+      const int e = e0 + u * 256 + t;
       if (e < nn) Ls[e] = v[u];
     }
   }
   __syncthreads();
+  if (t >= 64) return;
+  const int lane = t;
   const int i0 = lane, i1 = lane + 64;
   cx<double> y0 = {i0 == j ? 1.0 : 0.0, 0.0}, y1 = {i1 == j ? 1.0 : 0.0, 0.0};
   const double inv0 = (i0 >= j && i0 < n) ? 1.0 / Ls[i0 + (size_t)i0 * n].x : 0.0;
@@ -390,9 +411,16 @@ __global__ __launch_bounds__(64) void k_tri_inv(const cx<double>* __restrict__ L
   // rows beyond n and above k read zeros (the staged upper triangle is zero;
   // rows >= n are clamped), so the update needs no branch
   const int r0 = i0 < n ? i0 : n - 1, r1 = i1 < n ? i1 : n - 1;
+  // column k of L is read one step ahead (unconditionally; the rows at or
+  // above k are masked when used)
+  cx<double> n0 = Ls[r0 + j * n], n1 = Ls[r1 + j * n];
   for (int k = j; k < n; ++k) {
-    const cx<double> l0 = i0 > k ? Ls[r0 + k * n] : cx<double>{0.0, 0.0};
-    const cx<double> l1 = i1 > k && i1 < n ? Ls[r1 + k * n] : cx<double>{0.0, 0.0};
+    const cx<double> c0 = n0, c1 = n1;
+    const int kn = k + 1 < n ? k + 1 : k;
+    n0 = Ls[r0 + kn * n];
+    n1 = Ls[r1 + kn * n];
+    const cx<double> l0 = i0 > k ? c0 : cx<double>{0.0, 0.0};
+    const cx<double> l1 = i1 > k && i1 < n ? c1 : cx<double>{0.0, 0.0};
     const cx<double> own = k < 64 ? cx<double>{y0.x * inv0, y0.y * inv0}
                                   : cx<double>{y1.x * inv1, y1.y * inv1};
     const int src = k & 63;  // the same in every lane: a scalar read of the owner's value
@@ -441,7 +469,7 @@ ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>*
     ace_status st = launch(c, "chol_reg", k_chol_reg, dim3(1), dim3(threads), 0, M, n, s,
                            scratch, Lout, info_dev, prior, real_only ? 1 : 0);
     if (st != ACE_OK) return st;
-    return launch(c, "tri_inv", k_tri_inv, dim3(n), dim3(64), 0, (const cx<double>*)scratch, n,
+    return launch(c, "tri_inv", k_tri_inv, dim3(n), dim3(256), 0, (const cx<double>*)scratch, n,
                   C, (const int*)info_dev);
   }
   return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
