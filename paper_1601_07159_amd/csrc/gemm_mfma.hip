@@ -49,18 +49,6 @@ __device__ __forceinline__ int mfma_row(int l, int v) {
   return std::is_same<TAcc, double>::value ? (l >> 4) + 4 * v : 4 * (l >> 4) + v;
 }
 
-// Round-to-nearest-even FP32 -> BF16 on the bit pattern (finite inputs).
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_float(unsigned short h) {
-  return __uint_as_float((unsigned)h << 16);
-}
-__device__ __forceinline__ __bf16 as_bf16(unsigned short h) {
-  return __builtin_bit_cast(__bf16, h);
-}
 // (v1, -v0, v3, -v2, ...) of eight BF16 values, on the 32-bit words.
 __device__ __forceinline__ v8bf partner_neg(v8bf v) {
   typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -258,12 +246,12 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const unsigned short ah = bf16_bits(a[j][h][s]);
-          const unsigned short bh = bf16_bits(b[j][h][s]);
-          ahi[h][s] = as_bf16(ah);
-          alo[h][s] = as_bf16(bf16_bits(a[j][h][s] - bf16_to_float(ah)));
-          bhi[h][s] = as_bf16(bh);
-          blo[h][s] = as_bf16(bf16_bits(b[j][h][s] - bf16_to_float(bh)));
+          // round-to-nearest-even conversions (v_cvt_pk_bf16_f32)
+          const __bf16 ah = (__bf16)a[j][h][s], bh = (__bf16)b[j][h][s];
+          ahi[h][s] = ah;
+          alo[h][s] = (__bf16)(a[j][h][s] - (float)ah);
+          bhi[h][s] = bh;
+          blo[h][s] = (__bf16)(b[j][h][s] - (float)bh);
         }
       }
 #pragma unroll
