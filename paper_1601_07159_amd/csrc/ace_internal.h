@@ -173,11 +173,12 @@ ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ld
 // Dense stages (dense.hip).  Small matrices are complex128, column-major.
 // C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]   (real_part: imaginary part
 // written as 0; for real data viewed as complex pairs the real part is the
-// real dot product)
+// real dot product).  herm (na == nb, C Hermitian): only the 32 x 32 tiles on
+// or above the diagonal are computed, the others are their conjugates.
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
-                   bool real_part = false);
+                   bool real_part = false, bool herm = false);
 // Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K); c_upper: C is upper
 // triangular and its zero blocks are skipped
 template <typename T>

@@ -239,7 +239,8 @@ ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ld
   int* info = (int*)ws_take(c, 256, &st);
   if (!M || !X || !C || !info) return st;
   // M = dV psi^H W, then -M made exactly Hermitian
-  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed, real));
+  // M is Hermitian (V_X is): its upper triangle of tiles defines it
+  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed, real, true));
   // -M made exactly Hermitian, -M = L L^H, C = L^{-H}
   ACE_TRY(chol_inv(c, M, nb, -1.0, L_out, C, X, info, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true, true));
@@ -295,11 +296,11 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   cx<T>* Y = (cx<T>*)ws_take(c, tmp, &st);
   if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
   // round 1: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
-  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false, real));
+  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true, true));
   // round 2 on Y restores orthogonality lost to rounding in round 1
-  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false, real));
+  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1, real));
   ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true, true));
   return finish_info(c, info2, info_dev);

@@ -124,13 +124,42 @@ __device__ __forceinline__ TileRows<T> tile_rows(const cx<T>* A, long lda, int n
   return t;
 }
 
+// Hermitian mode (C = A^H A-like products whose lower triangle is the
+// conjugate of the upper one): the workgroup is one row of waves, wave w
+// taking the w-th tile on or above the diagonal, (0,0), (0,1), (1,1), (0,2),
+// ... (column-major over the upper triangle of tiles).
+template <typename T>
+__device__ __forceinline__ TileRows<T> tile_rows_herm(const cx<T>* A, long lda, int na,
+                                                      const cx<T>* B, long ldb, int nb, int r16) {
+  TileRows<T> t;
+  int ty = 0, tx = (int)(threadIdx.x >> 6);
+  while (tx > ty) {
+    tx -= ty + 1;
+    ++ty;
+  }
+  t.a0 = tx * 32;
+  t.b0 = ty * 32;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int ra = t.a0 + 16 * h + r16, rb = t.b0 + 16 * h + r16;
+    t.va[h] = ra < na;
+    t.vb[h] = rb < nb;
+    t.ba[h] = t.a0 + 16 * h < na;
+    t.bb[h] = t.b0 + 16 * h < nb;
+    t.pa[h] = A + (size_t)(t.va[h] ? ra : 0) * lda;
+    t.pb[h] = B + (size_t)(t.vb[h] ? rb : 0) * ldb;
+  }
+  return t;
+}
+
 template <typename T>
 __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
     const cx<T>* __restrict__ A, long lda, int na, const cx<T>* __restrict__ B, long ldb, int nb,
-    long K, long kchunk, cx<T>* __restrict__ partial) {
+    long K, long kchunk, cx<T>* __restrict__ partial, int herm) {
   typedef typename Acc4<T>::type acc_t;
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  const TileRows<T> t = tile_rows<T>(A, lda, na, B, ldb, nb, r16);
+  const TileRows<T> t = herm ? tile_rows_herm<T>(A, lda, na, B, ldb, nb, r16)
+                             : tile_rows<T>(A, lda, na, B, ldb, nb, r16);
   if (!t.ba[0] || !t.bb[0]) return;  // whole wave outside the output
   const long kbeg = (long)blockIdx.z * kchunk;
   const long kend = kbeg + kchunk < K ? kbeg + kchunk : K;
@@ -206,9 +235,11 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
 __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restrict__ A, long lda,
                                                          int na, const cx<float>* __restrict__ B,
                                                          long ldb, int nb, long K, long kchunk,
-                                                         cx<float>* __restrict__ partial) {
+                                                         cx<float>* __restrict__ partial,
+                                                         int herm) {
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
-  const TileRows<float> t = tile_rows<float>(A, lda, na, B, ldb, nb, r16);
+  const TileRows<float> t = herm ? tile_rows_herm<float>(A, lda, na, B, ldb, nb, r16)
+                                 : tile_rows<float>(A, lda, na, B, ldb, nb, r16);
   if (!t.ba[0] || !t.bb[0]) return;
   const long kbeg = (long)blockIdx.z * kchunk;
   const long kend = kbeg + kchunk < K ? kbeg + kchunk : K;
@@ -292,14 +323,33 @@ template <typename P>
 __global__ __launch_bounds__(1024) void k_reduce_partials2(const cx<P>* __restrict__ partial,
                                                            int ks, int na, int nb, double alpha,
                                                            cx<double>* __restrict__ C, int ldc,
-                                                           int real_part) {
+                                                           int real_part, int herm) {
   __shared__ double red[2][16][64];
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + el;
+  const int a = idx % na, b = idx / na;
+  // Hermitian mode: tiles below the diagonal were not computed; the entries
+  // of the tiles above it are written twice, the second time conjugated
+  const bool live = idx < na * nb && !(herm && a / 32 > b / 32);
   double sr = 0.0, si = 0.0;
-  if (idx < na * nb) {
-    for (int k = g; k < ks; k += 16) {
-      const cx<P> v = partial[(size_t)k * na * nb + idx];
+  if (live) {
+    const cx<P>* p = partial + idx;
+    const size_t step = (size_t)na * nb;
+    int k = g;
+    for (; k + 48 < ks; k += 64) {  // four partials in flight
+      const cx<P> v0 = p[k * step], v1 = p[(k + 16) * step];
+      const cx<P> v2 = p[(k + 32) * step], v3 = p[(k + 48) * step];
+      sr += (double)v0.x;
+      si += (double)v0.y;
+      sr += (double)v1.x;
+      si += (double)v1.y;
+      sr += (double)v2.x;
+      si += (double)v2.y;
+      sr += (double)v3.x;
+      si += (double)v3.y;
+    }
+    for (; k < ks; k += 16) {
+      const cx<P> v = p[k * step];
       sr += (double)v.x;
       si += (double)v.y;
     }
@@ -314,9 +364,10 @@ __global__ __launch_bounds__(1024) void k_reduce_partials2(const cx<P>* __restri
     }
     __syncthreads();
   }
-  if (g == 0 && idx < na * nb) {
-    const int a = idx % na, b = idx / na;
-    C[a + (size_t)b * ldc] = {alpha * red[0][0][el], real_part ? 0.0 : alpha * red[1][0][el]};
+  if (g == 0 && live) {
+    const double re = alpha * red[0][0][el], im = real_part ? 0.0 : alpha * red[1][0][el];
+    C[a + (size_t)b * ldc] = {re, im};
+    if (herm && a / 32 < b / 32) C[b + (size_t)a * ldc] = {re, -im};
   }
 }
 
@@ -569,21 +620,50 @@ static CnShape cn_shape(int na, int nb, long K, int max_waves, int cu_waves) {
   return s;
 }
 
+// Hermitian mode: one workgroup row of n_up = T(T+1)/2 waves (T tiles of 32
+// per side), as many workgroups per CU as cu_waves allows, one round.  Used
+// when n_up fits max_waves.
+static bool herm_shape(int n, long K, int max_waves, int cu_waves, CnShape* s) {
+  const int T = (n + 31) / 32, nup = T * (T + 1) / 2;
+  if (nup > max_waves) return false;
+  s->ta = nup;
+  s->tb = 1;
+  s->gx = s->gy = 1;
+  int per_cu = cu_waves / nup;
+  if (per_cu < 1) per_cu = 1;
+  long kchunk = (K + 256L * per_cu - 1) / (256L * per_cu);
+  kchunk = (kchunk + 63) / 64 * 64;
+  if (kchunk < 64) kchunk = 64;
+  s->kchunk = kchunk;
+  s->ks = (K + kchunk - 1) / kchunk;
+  if (s->ks < 1) s->ks = 1;
+  return true;
+}
+
 size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
-  const CnShape s32 = cn_shape(na, nb, K, 16, 16), s16 = cn_shape(na, nb, K, 12, 12);
-  const CnShape s64 = cn_shape(na, nb, K, 8, 12);
-  const size_t b32 = (size_t)(s32.ks > s16.ks ? s32.ks : s16.ks) * na * nb * sizeof(cx<float>);
-  const size_t b64 = (size_t)s64.ks * na * nb * sizeof(cx<double>);
+  CnShape s32 = cn_shape(na, nb, K, 16, 16), s16 = cn_shape(na, nb, K, 12, 12);
+  CnShape s64 = cn_shape(na, nb, K, 8, 12);
+  long k32 = s32.ks > s16.ks ? s32.ks : s16.ks, k64 = s64.ks;
+  if (na == nb) {
+    CnShape h;
+    if (herm_shape(na, K, 16, 16, &h) && h.ks > k32) k32 = h.ks;
+    if (herm_shape(na, K, 12, 12, &h) && h.ks > k32) k32 = h.ks;
+    if (herm_shape(na, K, 8, 12, &h) && h.ks > k64) k64 = h.ks;
+  }
+  const size_t b32 = (size_t)k32 * na * nb * sizeof(cx<float>);
+  const size_t b64 = (size_t)k64 * na * nb * sizeof(cx<double>);
   return align_up(b32 > b64 ? b32 : b64, 256);
 }
 
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
-                   bool real_part) {
-  const CnShape s = sizeof(T) == 8 ? cn_shape(na, nb, K, 8, 12)
-                    : bf16_split    ? cn_shape(na, nb, K, 12, 12)
-                                    : cn_shape(na, nb, K, 16, 16);
+                   bool real_part, bool herm) {
+  const int max_waves = sizeof(T) == 8 ? 8 : bf16_split ? 12 : 16;
+  const int cu_waves = sizeof(T) == 8 ? 12 : bf16_split ? 12 : 16;
+  CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
+  herm = herm && na == nb && herm_shape(na, K, max_waves, cu_waves, &s);
+  const int hm = herm ? 1 : 0;
   ace_status st;
   cx<T>* partial = (cx<T>*)ws_take(c, (size_t)s.ks * na * nb * sizeof(cx<T>), &st);
   if (!partial) return st;
@@ -592,20 +672,20 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
   if constexpr (std::is_same<T, float>::value) {
     if (bf16_split) {
       if ((st = launch(c, "cn_mfma_bf16x3", k_cn_mfma_bf16x3, grid, block, 0, A, lda, na, B, ldb,
-                       nb, K, s.kchunk, partial)) != ACE_OK)
+                       nb, K, s.kchunk, partial, hm)) != ACE_OK)
         return st;
     } else if ((st = launch(c, "cn_mfma_f32", k_cn_mfma<float>, grid, block, 0, A, lda, na, B,
-                            ldb, nb, K, s.kchunk, partial)) != ACE_OK) {
+                            ldb, nb, K, s.kchunk, partial, hm)) != ACE_OK) {
       return st;
     }
   } else {
     if ((st = launch(c, "cn_mfma_f64", k_cn_mfma<double>, grid, block, 0, A, lda, na, B, ldb, nb,
-                     K, s.kchunk, partial)) != ACE_OK)
+                     K, s.kchunk, partial, hm)) != ACE_OK)
       return st;
   }
   return launch(c, "reduce_partials", k_reduce_partials2<T>, dim3((na * nb + 63) / 64),
                 dim3(1024), 0, (const cx<T>*)partial, (int)s.ks, na, nb, alpha, C, ldc,
-                real_part ? 1 : 0);
+                real_part ? 1 : 0, hm);
 }
 
 template <typename TIn, typename TAcc>
@@ -651,9 +731,9 @@ ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>
 }
 
 template ace_status gemm_cn<float>(ace_ctx, const cx<float>*, long, int, const cx<float>*, long,
-                                   int, long, double, cx<double>*, int, bool, bool);
+                                   int, long, double, cx<double>*, int, bool, bool, bool);
 template ace_status gemm_cn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, long,
-                                    int, long, double, cx<double>*, int, bool, bool);
+                                    int, long, double, cx<double>*, int, bool, bool, bool);
 template ace_status gemm_nn<float>(ace_ctx, const cx<float>*, long, int, const cx<double>*, int,
                                    int, cx<float>*, long, long, bool, bool);
 template ace_status gemm_nn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, int,
