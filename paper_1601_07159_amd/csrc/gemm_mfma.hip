@@ -526,13 +526,16 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
         yim[x][y] = acc_t{0, 0, 0, 0};
       }
     cx<TIn> buf[R][XB];
+    // Unconditional loads from clamped addresses: an orbital past n_a meets
+    // zero rows of C, a grid row past K is not stored, a step past the last
+    // is not used.  (A conditional load makes the compiler wait for it at
+    // once, which serialises the pipeline.)
     auto load = [&](cx<TIn> (&v)[XB], int st) {
-      const int a = 4 * st + kq;
+      const int a = 4 * st + kq < na ? 4 * st + kq : na - 1;
 #pragma unroll
       for (int x = 0; x < XB; ++x) {
         const long r = rt0 + 16 * x + r16;
-        v[x] = {TIn(0), TIn(0)};
-        if (st < nsteps && a < na && r < K) v[x] = A[(size_t)a * lda + r];
+        v[x] = A[(size_t)a * lda + (r < K ? r : K - 1)];
       }
     };
     // C entries of a step, read from LDS one step ahead of their use (the
