@@ -148,7 +148,8 @@ template <typename T>
 ace_status build_W_real_impl(ace_ctx c, const GridInfo& g, const T* phi, int nocc, long ldphi,
                              const T* psi, int nband, long ldpsi, T* W, long ldW, double scale,
                              const double* dscale = nullptr);
-BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband);
+BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband,
+                          bool psi_starts_with_phi);
 
 // Argument checks shared by the entry points (api.hip).
 ace_status check_grid(ace_ctx c, const ace_grid* g, ace_prec prec, GridInfo* out);

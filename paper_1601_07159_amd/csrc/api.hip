@@ -432,8 +432,11 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   const size_t mat = align_up((size_t)nmax * nmax * sizeof(cx<double>), 256);
   if (is_real(prec)) {
     const GridInfo gh = half_view(g);
-    size_t need = plan_build_real(c, g, 2 * eb, max_nocc, max_nband).bytes;
-    need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nocc).bytes);
+    size_t need = 0;
+    for (int symm = 0; symm < 2; ++symm) {
+      need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nband, symm).bytes);
+      need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nocc, symm).bytes);
+    }
     need = std::max(need, compress_ws_bytes(max_nband, gh.ng));
     need = std::max(need, orth_ws_bytes(nmax, gh.ng, 2 * eb));
     need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), gh.ng));

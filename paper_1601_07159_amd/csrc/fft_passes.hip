@@ -88,6 +88,21 @@ __device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
   }
 }
 
+// Units of the packed real triangle before column c: sum over c' < c of
+// (floor(c'/2) + 1).
+__host__ __device__ __forceinline__ long real_tri_units(int c) {
+  const long q = c / 2;
+  return c + ((c & 1) ? q * q : q * (q - 1));
+}
+// Column c and row pair m of triangle unit p (p < real_tri_units(n)).
+__device__ __forceinline__ void real_tri_of(long p, int* c, int* m) {
+  int cc = (int)(2.0 * sqrt((double)p));  // close to the root of c^2/4 + c/2 = p
+  while (cc > 0 && real_tri_units(cc) > p) --cc;
+  while (real_tri_units(cc + 1) <= p) ++cc;
+  *c = cc;
+  *m = (int)(p - real_tri_units(cc));
+}
+
 // Pair of block-local index p.
 //  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
 //  mode 1: upper triangle i <= j of a diagonal block starting at i0 (= j0),
@@ -449,11 +464,13 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
 // two pairs (the plane pass is shared with the complex path).
 // Unit p of a chunk: orbitals a = i0 + 2m, b = a + 1 (absent when 2m + 1 = A)
 // with m = p % Am, band j = j0 + p / Am.
+// sym = 1: the packed triangle of the occupied block (psi = phi there), then
+// the rectangle of the extra bands j0 = A, ... (units as in plan_build_real).
 template <int N, typename T>
 __global__ __launch_bounds__(N) void k_pair_fwd_real_t1(const T* __restrict__ phi, long ldphi,
                                                         const T* __restrict__ psi, long ldpsi,
                                                         cx<T>* __restrict__ buf, int i0, int A,
-                                                        int Am, int j0, int nunits) {
+                                                        int Am, int j0, int nunits, int sym) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
   __shared__ cx<T> s[N * LD];
@@ -461,12 +478,25 @@ __global__ __launch_bounds__(N) void k_pair_fwd_real_t1(const T* __restrict__ ph
   if (lid >= (long)N * nunits) return;
   const int x0 = (int)(lid / nunits);
   const int p = (int)(lid - (long)x0 * nunits);
-  const int m = p % Am, b = p / Am;
-  const int ia = i0 + 2 * m;
-  const bool has_b = 2 * m + 1 < A;
+  int ia, jb;
+  bool has_b;
+  const long tri = sym ? real_tri_units(A) : 0;
+  if (p < tri) {
+    int cc, mm;
+    real_tri_of(p, &cc, &mm);
+    ia = 2 * mm;
+    has_b = 2 * mm + 1 <= cc;
+    jb = cc;
+  } else {
+    const int q = (int)(p - tri);
+    const int m = q % Am;
+    ia = i0 + 2 * m;
+    has_b = 2 * m + 1 < A;
+    jb = j0 + q / Am;
+  }
   const T* fa = phi + (size_t)ia * ldphi + (size_t)x0 * NN;
   const T* fb = has_b ? fa + ldphi : fa;
-  const T* ps = psi + (size_t)(j0 + b) * ldpsi + (size_t)x0 * NN;
+  const T* ps = psi + (size_t)jb * ldpsi + (size_t)x0 * NN;
   const int t = threadIdx.x;
   {
     // issue every load of the slab before the first use
@@ -550,6 +580,136 @@ __global__ __launch_bounds__(64) void k_pencil_accum_real(const T* __restrict__ 
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) w[k * N] = acc[k * 64 + t];
+  }
+}
+
+// Accumulate pass of the symmetric real chunk.  Workgroup row g < G = ceil(A/2)
+// owns the band pair (j0, j1) = (2g, 2g + 1) of the occupied block (j1
+// absent when it reaches A) with two LDS accumulators, so that a unit of a
+// column c > j1, which holds u_{j0 c} (real part) and u_{j1 c} (imaginary
+// part), is read once for both bands:
+//   column j0, units m <= g:    w_j0 += phi_2m u_{2m j0} + phi_2m+1 u_{2m+1 j0}
+//   column j1, units m < g:     w_j1 += phi_2m u_{2m j1} + phi_2m+1 u_{2m+1 j1}
+//   column j1, unit g:          w_j0 += phi_j1 u_{j0 j1},
+//                               w_j1 += phi_j0 u_{j0 j1} + phi_j1 u_{j1 j1}
+//   columns c > j1, unit g:     w_j0 += phi_c u_{j0 c},  w_j1 += phi_c u_{j1 c}
+// (u_ij = u_ji for real fields).  Rows g >= G are the extra bands A + (g - G),
+// accumulated from their rectangle units as in k_pencil_accum_real.
+// Two waves per SIMD where the registers allow it without spills (FP32 up to
+// N = 48); the compiler would otherwise settle for one at N = 48.
+template <int N, typename T>
+constexpr int kRealSymWaves = (sizeof(T) == 4 && N <= 48) ? 2 : 1;
+template <int N, typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kRealSymWaves<N, T>))) void
+k_pencil_accum_real_sym(const T* __restrict__ phi,
+                                                              long ldphi,
+                                                              const cx<T>* __restrict__ buf,
+                                                              T* __restrict__ W, long ldW, int A,
+                                                              int nrows) {
+  constexpr int NN = N * N;
+  constexpr int TILES = (NN + 63) / 64;
+  __shared__ T acc0[N * 64];
+  __shared__ T acc1[N * 64];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)TILES * nrows) return;
+  const int tile = (int)(lid / nrows);
+  const int g = (int)(lid - (long)tile * nrows);
+  const int t = threadIdx.x;
+  const int q = tile * 64 + t;
+  if (q >= NN) return;
+  const int x0 = q / N, x2 = q - x0 * N;
+  const size_t off = (size_t)x0 * NN + x2;
+  const int G = (A + 1) / 2;
+  const long tri = real_tri_units(A);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    acc0[k * 64 + t] = T(0);
+    acc1[k * 64 + t] = T(0);
+  }
+  // inverse FFT along axis 1 of unit u at this pencil
+  auto unit = [&](long u, cx<T> (&v)[N]) {
+    const cx<T>* src = buf + (size_t)u * N * NN + off;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] = src[k * N];
+    fft_line<N, +1, T>(v);
+  };
+  // acc += fa * Re v + wb * fb * Im v
+  auto add2 = [&](T* acc, const T* pa, const T* pb, T wb, const cx<T> (&v)[N]) {
+    T fa[N], fb[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) fa[k] = pa[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) fb[k] = pb[k * N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) acc[k * 64 + t] += fa[k] * v[k].x + wb * fb[k] * v[k].y;
+  };
+  cx<T> v[N];
+  if (g < G) {
+    const int j0 = 2 * g, j1 = 2 * g + 1;
+    const bool two = j1 < A;
+    // column j0
+    for (int m = 0; m <= g; ++m) {
+      unit(real_tri_units(j0) + m, v);
+      const T* pa = phi + (size_t)(2 * m) * ldphi + off;
+      const bool hb = 2 * m + 1 <= j0;
+      add2(acc0, pa, hb ? pa + ldphi : pa, hb ? T(1) : T(0), v);
+    }
+    if (two) {
+      // column j1, rows below j0
+      for (int m = 0; m < g; ++m) {
+        unit(real_tri_units(j1) + m, v);
+        const T* pa = phi + (size_t)(2 * m) * ldphi + off;
+        add2(acc1, pa, pa + ldphi, T(1), v);
+      }
+      // unit (j0, j1; column j1)
+      unit(real_tri_units(j1) + g, v);
+      const T* p0 = phi + (size_t)j0 * ldphi + off;
+      const T* p1 = p0 + ldphi;
+      {
+        T f0[N], f1[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) f0[k] = p0[k * N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) f1[k] = p1[k * N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          acc0[k * 64 + t] += f1[k] * v[k].x;
+          acc1[k * 64 + t] += f0[k] * v[k].x + f1[k] * v[k].y;
+        }
+      }
+    }
+    // columns beyond the pair
+    for (int c = two ? j1 + 1 : j0 + 1; c < A; ++c) {
+      unit(real_tri_units(c) + g, v);
+      const T* pc = phi + (size_t)c * ldphi + off;
+      T fc[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) fc[k] = pc[k * N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        acc0[k * 64 + t] += fc[k] * v[k].x;
+        acc1[k * 64 + t] += fc[k] * v[k].y;
+      }
+    }
+    T* w0 = W + (size_t)j0 * ldW + off;
+#pragma unroll
+    for (int k = 0; k < N; ++k) w0[k * N] = acc0[k * 64 + t];
+    if (two) {
+      T* w1 = W + (size_t)j1 * ldW + off;
+#pragma unroll
+      for (int k = 0; k < N; ++k) w1[k * N] = acc1[k * 64 + t];
+    }
+  } else {
+    const int b = g - G;  // extra band A + b
+    for (int m = 0; m < G; ++m) {
+      unit(tri + m + (long)G * b, v);
+      const T* pa = phi + (size_t)(2 * m) * ldphi + off;
+      const bool hb = 2 * m + 1 < A;
+      add2(acc0, pa, hb ? pa + ldphi : pa, hb ? T(1) : T(0), v);
+    }
+    T* w = W + (size_t)(A + b) * ldW + off;
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k * N] = acc0[k * 64 + t];
   }
 }
 
@@ -715,7 +875,15 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
 
 // Real orbitals: units of two pairs; A orbitals (even unless all of them) x B
 // bands per chunk, Am = ceil(A / 2) units per band.
-BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband) {
+// Real orbitals with psi's first n_occ orbitals equal to phi: u_ij = u_ji on
+// the occupied block, so only pairs i <= j are transformed.  Column c of the
+// triangle packs rows (2m, 2m + 1), 2m <= c, into unit real_tri_units(c) + m
+// (row 2m + 1 absent when it exceeds c); the extra bands follow as rectangle
+// units (orbital pair m, band n_occ + k) at real_tri_units(n_occ) + m + Am k.
+// Used when all units fit the pair budget (one chunk); otherwise the rectangle
+// chunks below.
+BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int nocc, int nband,
+                          bool psi_starts_with_phi) {
   BuildPlan pl;
   const size_t unit_bytes = (size_t)g.ng * cx_bytes;
   size_t budget = c->pair_budget;
@@ -723,15 +891,25 @@ BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int noc
   if (!budget) budget = default_pair_budget();
   long maxunits = (long)(budget / unit_bytes);
   if (maxunits < 1) maxunits = 1;
-  int B = jblock > 0 ? (int)std::min<long>(nband, jblock) : nband;
-  B = (int)std::max<long>(1, std::min<long>(B, maxunits));
-  long am = std::max<long>(1, std::min<long>((nocc + 1) / 2, maxunits / B));
-  pl.B = B;
-  pl.A = (int)std::min<long>(nocc, 2 * am);
-  pl.sym = false;
   pl.symblk = 0;
   pl.merged = false;
-  pl.pairs_alloc = (size_t)((pl.A + 1) / 2) * pl.B;
+  const long sym_units = real_tri_units(nocc) + (long)((nocc + 1) / 2) * (nband - nocc);
+  if (c->use_symmetry && psi_starts_with_phi && nocc >= 2 && jblock == 0 &&
+      sym_units <= maxunits) {
+    pl.sym = true;
+    pl.merged = true;
+    pl.A = nocc;
+    pl.B = nband;
+    pl.pairs_alloc = (size_t)sym_units;
+  } else {
+    int B = jblock > 0 ? (int)std::min<long>(nband, jblock) : nband;
+    B = (int)std::max<long>(1, std::min<long>(B, maxunits));
+    long am = std::max<long>(1, std::min<long>((nocc + 1) / 2, maxunits / B));
+    pl.B = B;
+    pl.A = (int)std::min<long>(nocc, 2 * am);
+    pl.sym = false;
+    pl.pairs_alloc = (size_t)((pl.A + 1) / 2) * pl.B;
+  }
   pl.bytes = align_up((size_t)g.ng * std::max<size_t>(cx_bytes / 2, 4), 256) +
              align_up(pl.pairs_alloc * unit_bytes, 256);
   return pl;
@@ -895,7 +1073,10 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   const size_t unit_bytes = (size_t)g.ng * sizeof(cx<T>);
-  const BuildPlan pl = plan_build_real(c, g, sizeof(cx<T>), nocc, nband);
+  // the symmetric accumulate kernel spills heavily in FP64 above N = 48
+  const bool sym_ok = sizeof(T) == 4 || N <= 48;
+  const BuildPlan pl =
+      plan_build_real(c, g, sizeof(cx<T>), nocc, nband, sym_ok && psi == phi && ldpsi == ldphi);
   const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
   if ((st = ws_begin(c, pl.bytes)) != ACE_OK) return st;
@@ -904,6 +1085,17 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
   if (!Kt || !buf) return st;
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
   const bool quad_p = use_quad<N, T>(c, true);
+  if (pl.sym) {
+    const int G = (nocc + 1) / 2, nu = (int)pl.pairs_alloc;
+    if ((st = launch(c, "pair_fwd_real", k_pair_fwd_real_t1<N, T>, dim3(xcd_pad((long)N * nu)),
+                     dim3(N), 0, phi, ldphi, psi, ldpsi, buf, 0, nocc, G, nocc, nu, 1)) != ACE_OK)
+      return st;
+    if ((st = plane<N, T>(c, quad_p, buf, Kt, nu)) != ACE_OK) return st;
+    const int nrows = G + (nband - nocc);
+    return launch(c, "pencil_accum_real", k_pencil_accum_real_sym<N, T>,
+                  dim3(xcd_pad((long)TILES * nrows)), dim3(64), 0, phi, ldphi, (const cx<T>*)buf,
+                  W, ldW, nocc, nrows);
+  }
   for (int j0 = 0; j0 < nband; j0 += pl.B) {
     const int Bc = std::min(pl.B, nband - j0);
     for (int i0 = 0; i0 < nocc; i0 += pl.A) {
@@ -912,7 +1104,7 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
       const int nu = Am * Bc;
       if ((st = launch(c, "pair_fwd_real", k_pair_fwd_real_t1<N, T>,
                        dim3(xcd_pad((long)N * nu)), dim3(N), 0, phi, ldphi, psi, ldpsi, buf, i0,
-                       Ac, Am, j0, nu)) != ACE_OK)
+                       Ac, Am, j0, nu, 0)) != ACE_OK)
         return st;
       if ((st = plane<N, T>(c, quad_p, buf, Kt, nu)) != ACE_OK) return st;
       if ((st = launch(c, "pencil_accum_real", k_pencil_accum_real<N, T>,

@@ -62,6 +62,26 @@ def test_build_W_real_chunked(ace, prec):
 
 
 @pytest.mark.parametrize("prec", ["real64", "real32"])
+@pytest.mark.parametrize("n,nocc,nband", [(16, 9, 13), (24, 8, 8), (12, 2, 5), (16, 13, 13)])
+def test_build_W_real_symmetric_packing(ace, prec, n, nocc, nband):
+    # psi's first n_occ orbitals are phi: only the pairs i <= j of the occupied
+    # block are transformed (two per unit) and each unit serves both bands;
+    # the same build with the symmetry switched off takes the rectangle chunks
+    L = 0.43 * n
+    psi = synth.real_orbitals(n, L, nband, seed=31 * n + nocc)
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L))
+    x = to_gpu(psi, prec)
+    ctx = ace.Context()
+    Ws = ctx.build_W(x[:nocc], x, ggrid(n, L), prec)
+    ctx.set_tuning("symmetry", 0)
+    Wr = ctx.build_W(x[:nocc], x, ggrid(n, L), prec)
+    ctx.close()
+    assert rel(_np(Ws), ref.real) <= tol(prec)
+    assert rel(_np(Wr), ref.real) <= tol(prec)
+    assert rel(_np(Ws), _np(Wr)) <= tol(prec)
+
+
+@pytest.mark.parametrize("prec", ["real64", "real32"])
 def test_real_compress_apply_energy(ace, prec):
     import torch
     n, L, nocc, nband = 24, 10.0, 6, 10
