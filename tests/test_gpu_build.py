@@ -178,3 +178,29 @@ def test_config2_full_size_sampled(ace):
     assert abs(e_ace - e_ref) <= 1e-5 * abs(e_ref)
     assert abs(e_dir - e_ref) <= 1e-5 * abs(e_ref)
     torch.cuda.synchronize()
+
+
+def test_config3_full_size_sampled(ace):
+    """72^3, L = 30.8, N_occ = 216, N_band = 256, erfc-screened kernel (mu = 0.106),
+    FP32, in the bench's launch configuration (blocked symmetry chunks): one
+    occupied and one virtual column of W against the oracle, then the ACE
+    condition V_ACE psi = W and the two energy forms against each other."""
+    import torch
+    n, L, nocc, nband, mu = 72, 30.8, 216, 256, 0.106
+    print(f"config3 full size n={n} nocc={nocc} nband={nband}", flush=True)
+    psi = synth.smooth_orbitals(n, L, nband, seed=3)
+    g = ggrid(n, L, "erfc", mu)
+    x = to_gpu(psi, "fp32")
+    W = ace.build_W(x[:nocc], x, g, "fp32")
+    cols = [101, 240]
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L, "erfc", mu), columns=cols)
+    Wn = to_np(W)
+    for k, j in enumerate(cols):
+        assert rel(Wn[j], ref[k]) <= 1e-5, j
+    xi = ace.compress(x, W, g, "fp32")
+    Y = ace.apply(xi, x, g, "fp32")
+    assert rel(to_np(Y), Wn) <= 1e-5
+    e_ace = float(ace.exchange_energy(x[:nocc], g, "fp32", xi=xi).item())
+    e_dir = float(ace.exchange_energy(x[:nocc], g, "fp32").item())
+    assert abs(e_ace - e_dir) <= 1e-5 * abs(e_dir)
+    torch.cuda.synchronize()

@@ -136,3 +136,22 @@ def test_real_rejects(ace):
     with pytest.raises(ace.AceError) as e:
         ace.exchange_energy(y, gg, "real64")  # direct form: complex only
     assert e.value.status == 5
+
+
+def test_config2_real_full_size_sampled(ace):
+    """48^3, L = 20.5, N_occ = 64, N_band = 80 with real orbitals (REAL32), in the
+    bench's launch configuration (symmetric packed units): sampled columns of W
+    against the oracle and the ACE condition V_ACE psi = W."""
+    n, L, nocc, nband = 48, 20.5, 64, 80
+    psi = synth.real_orbitals(n, L, nband, seed=0)
+    g = ggrid(n, L)
+    x = to_gpu(psi, "real32")
+    W = ace.build_W(x[:nocc], x, g, "real32")
+    cols = [0, 31, 63, 64, 79]
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L), columns=cols)
+    Wn = _np(W)
+    for k, j in enumerate(cols):
+        assert rel(Wn[j], ref[k].real) <= 1e-5, j
+    xi = ace.compress(x, W, g, "real32")
+    Y = ace.apply(xi, x, g, "real32")
+    assert rel(_np(Y), Wn) <= 1e-5
