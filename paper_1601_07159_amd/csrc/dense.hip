@@ -26,6 +26,9 @@ namespace {
 //             finished blocks of X kept (conjugate-transposed) in C.
 // lda >= n; T is scratch of kCholNB x n.
 constexpr int kCholNB = 16;
+// Up to this n the current panel (n x kCholNB) is staged in LDS.
+constexpr int kCholPanelRows = 512;
+__shared__ cx<double> chol_panel[kCholNB][kCholPanelRows];
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -67,6 +70,87 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
   // ---- Cholesky, right-looking by panels
   for (int kb = 0; kb < n; kb += NB) {
     const int nb = n - kb < NB ? n - kb : NB;
+    if (n <= kCholPanelRows) {
+      // the panel (rows kb.., columns kb..kb+nb-1) in LDS: P[c][r] = A[kb + r][kb + c]
+      cx<double> (*P)[kCholPanelRows] = chol_panel;
+      const int R = n - kb;
+      for (int e = t; e < nb * R; e += nt) {
+        const int c = e / R, r = e - c * R;
+        P[c][r] = A[(kb + r) + (size_t)(kb + c) * lda];
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int k = 0; k < nb; ++k) {
+          const double d = P[k][k].x;
+          if (!(d > 0.0) || !isfinite(d)) {
+            if (lane == 0) failed = kb + k + 1;
+            break;  // uniform across the wave
+          }
+          const double r = sqrt(d), inv = 1.0 / r;
+          wave_sync();
+          if (lane == 0) P[k][k] = {r, 0.0};
+          const int i = k + 1 + lane;
+          if (i < nb) {
+            const cx<double> v = P[k][i];
+            P[k][i] = {v.x * inv, v.y * inv};
+          }
+          wave_sync();
+          const int m = nb - k - 1;
+          for (int e = lane; e < m * m; e += 64) {
+            const int ii = k + 1 + e % m, jj = k + 1 + e / m;
+            if (ii < jj) continue;
+            const cx<double> u = cmulcj_d(P[k][ii], P[k][jj]);
+            const cx<double> v = P[jj][ii];
+            P[jj][ii] = {v.x - u.x, v.y - u.y};
+          }
+          wave_sync();
+        }
+      }
+      __syncthreads();
+      if (failed) break;
+      // rows below the diagonal block: x L_kk^H = a, one thread per row
+      for (int r = nb + t; r < R; r += nt) {
+        cx<double> x[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[c] = c < nb ? P[c][r] : cx<double>{0, 0};
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (c >= nb) break;
+          cx<double> v = x[c];
+#pragma unroll
+          for (int d = 0; d < c; ++d) {
+            const cx<double> u = cmulcj_d(x[d], P[d][c]);
+            v.x -= u.x;
+            v.y -= u.y;
+          }
+          const double inv = 1.0 / P[c][c].x;
+          x[c] = {v.x * inv, v.y * inv};
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c < nb) P[c][r] = x[c];
+      }
+      __syncthreads();
+      // the finished panel back to A; the trailing lower triangle from the
+      // LDS panel (disjoint columns of A)
+      for (int e = t; e < nb * R; e += nt) {
+        const int c = e / R, r = e - c * R;
+        if (r >= c) A[(kb + r) + (size_t)(kb + c) * lda] = P[c][r];
+      }
+      for (int j = kb + nb + wave; j < n; j += nw)
+        for (int i = j + lane; i < n; i += 64) {
+          cx<double> acc = A[i + (size_t)j * lda];
+          for (int c = 0; c < nb; ++c) {
+            const cx<double> u = cmulcj_d(P[c][i - kb], P[c][j - kb]);
+            acc.x -= u.x;
+            acc.y -= u.y;
+          }
+          A[i + (size_t)j * lda] = acc;
+        }
+      __syncthreads();
+      continue;
+    }
+    // n > kCholPanelRows: the panel stays in global memory
     if (wave == 0) {
       for (int k = kb; k < kb + nb; ++k) {
         const double d = A[k + (size_t)k * lda].x;
@@ -185,6 +269,59 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
     }
   for (int ib = 1; ib < nbk; ++ib) {
     const int ri = ib * NB, ni = n - ri < NB ? n - ri : NB;
+    if (n <= kCholPanelRows) {
+      // block row ib of L (columns < ri) and X_ii staged in LDS:
+      // Lr[r][k] = L[ri + r][k] for k < ri, Lr[r][ri + q] = X_ii[r][q] (q <= r)
+      cx<double> (*Lr)[kCholPanelRows] = chol_panel;
+      const int w = ri + ni;
+      for (int e = t; e < ni * w; e += nt) {
+        const int r = e / w, k = e - r * w;
+        Lr[r][k] = A[(ri + r) + (size_t)k * lda];
+      }
+      __syncthreads();
+      // one thread per column: T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]
+      // for all r of the block row, then X[ri + r][col] = -sum_{q <= r} X_ii[r][q] T[q][col]
+      for (int col = t; col < ri; col += nt) {
+        cx<double> acc[NB];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[r] = {0.0, 0.0};
+        const int cb_end = (col / NB + 1) * NB;  // X[k][col] for k < cb_end: diagonal block
+        for (int k = col; k < ri; ++k) {
+          // the diagonal block holds X in place; finished blocks hold conj(X) in the
+          // upper triangle of A
+          cx<double> x;
+          if (k < cb_end) {
+            x = A[k + (size_t)col * lda];
+          } else {
+            const cx<double> xc = A[col + (size_t)k * lda];
+            x = {xc.x, -xc.y};
+          }
+#pragma unroll
+          for (int r = 0; r < NB; ++r) {
+            const cx<double> u = cmul_d(Lr[r][k], x);
+            acc[r].x += u.x;
+            acc[r].y += u.y;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+          if (r >= ni) break;
+          cx<double> sm = {0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q <= r; ++q) {
+            const cx<double> u = cmul_d(Lr[r][ri + q], acc[q]);
+            sm.x += u.x;
+            sm.y += u.y;
+          }
+          const cx<double> xc = {-sm.x, sm.y};  // conj(X[ri + r][col])
+          A[col + (size_t)(ri + r) * lda] = xc;
+          C[col + (size_t)(ri + r) * n] = xc;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    // n > kCholPanelRows: everything from global memory
     // T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]
     for (int col = wave; col < ri; col += nw)
       for (int r = lane; r < ni; r += 64) {

@@ -420,38 +420,51 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
     }
     __syncthreads();
     const int steps = (na - ac) < KC ? (na - ac + 3) / 4 : KC / 4;
-    // four 4-orbital steps per group: all their A loads are issued first
-    for (int st0 = 0; st0 < steps; st0 += 4) {
-      TAcc xr[4][XB], xi[4][XB];
+    const int ngroups = (steps + 3) / 4;
+    // Groups of four 4-orbital steps, double-buffered: the A loads of group
+    // g + 1 are in flight while group g is multiplied.  Loads are
+    // unconditional from clamped addresses (an orbital past n_a meets zero
+    // rows of C, a grid row past K is not stored, a group past the last
+    // re-reads it), so the compiler keeps them in flight.
+    auto loadg = [&](cx<TIn> (&v)[4][XB], int grp) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int a = ac + 4 * (st0 + u) + kq;
+        const int a = ac + 4 * (4 * grp + u) + kq;
+        const int ac_ = a < na ? a : na - 1;
 #pragma unroll
         for (int x = 0; x < XB; ++x) {
           const long r = rt0 + 16 * x + r16;
-          cx<TIn> v = {TIn(0), TIn(0)};
-          if (st0 + u < steps && a < na && r < K) v = A[(size_t)a * lda + r];
-          xr[u][x] = (TAcc)v.x;
-          xi[u][x] = (TAcc)v.y;
+          v[u][x] = A[(size_t)ac_ * lda + (r < K ? r : K - 1)];
         }
       }
+    };
+    auto mulg = [&](const cx<TIn> (&v)[4][XB], int grp) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (st0 + u >= steps) break;
-        const int st = st0 + u;
+        const int st = 4 * grp + u;
+        if (st >= steps) break;
 #pragma unroll
         for (int y = 0; y < NBB; ++y) {
           const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
           const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
 #pragma unroll
           for (int x = 0; x < XB; ++x) {
-            yre[x][y] = mfma4(xr[u][x], cr, yre[x][y]);
-            yre[x][y] = mfma4(xi[u][x], -ci, yre[x][y]);
-            yim[x][y] = mfma4(xr[u][x], ci, yim[x][y]);
-            yim[x][y] = mfma4(xi[u][x], cr, yim[x][y]);
+            const TAcc xr = (TAcc)v[u][x].x, xi = (TAcc)v[u][x].y;
+            yre[x][y] = mfma4(xr, cr, yre[x][y]);
+            yre[x][y] = mfma4(xi, -ci, yre[x][y]);
+            yim[x][y] = mfma4(xr, ci, yim[x][y]);
+            yim[x][y] = mfma4(xi, cr, yim[x][y]);
           }
         }
       }
+    };
+    cx<TIn> xa[4][XB], xb[4][XB];
+    loadg(xa, 0);
+    for (int grp = 0; grp < ngroups; grp += 2) {
+      loadg(xb, grp + 1 < ngroups ? grp + 1 : grp);
+      mulg(xa, grp);
+      loadg(xa, grp + 2 < ngroups ? grp + 2 : ngroups - 1);
+      if (grp + 1 < ngroups) mulg(xb, grp + 1);
     }
     __syncthreads();
   }
