@@ -126,9 +126,10 @@ def test_config1_full_fp64(ace):
     assert abs(e - gold["E_X_coulomb"]) <= 1e-10 * abs(gold["E_X_coulomb"])
 
 
-@pytest.mark.parametrize("nocc,nband", [(50, 81), (50, 88), (60, 96), (60, 100)])
+@pytest.mark.parametrize("nocc,nband", [(50, 81), (50, 88), (60, 96), (60, 100), (8, 520)])
 def test_compress_large_bands_both_factorisation_paths(ace, nocc, nband):
-    # n_band <= 88 factorises in registers, larger n_band in global scratch
+    # n_band <= 88 factorises in registers, larger n_band in global scratch with
+    # the panels staged in LDS up to 512, beyond that from global memory
     import torch
     n, L = 16, 7.5
     psi = synth.smooth_orbitals(n, L, nband, seed=nband)
