@@ -49,6 +49,11 @@ __device__ __forceinline__ int mfma_row(int l, int v) {
   return std::is_same<TAcc, double>::value ? (l >> 4) + 4 * v : 4 * (l >> 4) + v;
 }
 
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+// Third word of a raw buffer resource (32-bit data, no swizzle): loads past
+// num_records return zero.
+constexpr int kBufferFlags = 0x00020000;
+
 // (v1, -v0, v3, -v2, ...) of eight BF16 values, on the 32-bit words.
 __device__ __forceinline__ v8bf partner_neg(v8bf v) {
   typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -252,35 +257,53 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
       cim[x][y] = v4f{0, 0, 0, 0};
     }
   // Two-slot pipeline over 16-point steps: the raw loads of step i + 1 are
-  // issued before step i is split into BF16 halves and multiplied.
+  // issued before step i is split into BF16 halves and multiplied.  Loads go
+  // through per-wave buffer resources spanning the tile's rows inside the
+  // output: rows outside it fall past the resource and read zero without a
+  // memory access, so no load is conditional (a conditional load makes the
+  // compiler wait for every load in flight).  Points past the chunk are
+  // zeroed when used (kin bits).
+  const int nva = na - t.a0 < 32 ? na - t.a0 : 32, nvb = nb - t.b0 < 32 ? nb - t.b0 : 32;
+  const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(A + (size_t)t.a0 * lda), (short)0, (int)((long)nva * lda * 8), kBufferFlags);
+  const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(B + (size_t)t.b0 * ldb), (short)0, (int)((long)nvb * ldb * 8), kBufferFlags);
   float a[2][2][8], b[2][2][8];
-  auto load = [&](float (&ar)[2][8], float (&br)[2][8], long k) {
+  unsigned kin[2];
+  auto load = [&](float (&ar)[2][8], float (&br)[2][8], unsigned& in, long k) {
+    in = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) in |= (k + q < kend ? 1u : 0u) << q;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      const long ea = (long)(16 * h + r16) * lda + k, eb = (long)(16 * h + r16) * ldb + k;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        cx<float> x = {0.f, 0.f}, y = {0.f, 0.f};
-        if (k + q < kend && t.va[h]) x = t.pa[h][k + q];
-        if (k + q < kend && t.vb[h]) y = t.pb[h][k + q];
-        ar[h][2 * q] = x.x; ar[h][2 * q + 1] = x.y;
-        br[h][2 * q] = y.x; br[h][2 * q + 1] = y.y;
+      for (int q = 0; q < 4; q += 2) {
+        const v4u va = __builtin_amdgcn_raw_buffer_load_b128(rsa, (int)((ea + q) * 8), 0, 0);
+        const v4u vb = __builtin_amdgcn_raw_buffer_load_b128(rsb, (int)((eb + q) * 8), 0, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          ar[h][2 * q + c] = __uint_as_float(va[c]);
+          br[h][2 * q + c] = __uint_as_float(vb[c]);
+        }
       }
     }
   };
-  load(a[0], b[0], kbeg + 4 * kq);
+  load(a[0], b[0], kin[0], kbeg + 4 * kq);
   for (long k0 = kbeg; k0 < kend; k0 += 32) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      load(a[j ^ 1], b[j ^ 1], k0 + 16 * (j + 1) + 4 * kq);
+      load(a[j ^ 1], b[j ^ 1], kin[j ^ 1], k0 + 16 * (j + 1) + 4 * kq);
       v8bf ahi[2], alo[2], bhi[2], blo[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
+          const float av = (kin[j] >> (s >> 1)) & 1u ? a[j][h][s] : 0.f;
           // round-to-nearest-even conversions (v_cvt_pk_bf16_f32)
-          const __bf16 ah = (__bf16)a[j][h][s], bh = (__bf16)b[j][h][s];
+          const __bf16 ah = (__bf16)av, bh = (__bf16)b[j][h][s];
           ahi[h][s] = ah;
-          alo[h][s] = (__bf16)(a[j][h][s] - (float)ah);
+          alo[h][s] = (__bf16)(av - (float)ah);
           bhi[h][s] = bh;
           blo[h][s] = (__bf16)(b[j][h][s] - (float)bh);
         }
@@ -695,6 +718,10 @@ template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
                    bool real_part, bool herm) {
+  // the BF16-split kernel addresses a tile's 32 rows through a buffer
+  // resource with 32-bit byte offsets
+  if (bf16_split && (lda > (1L << 31) / 256 || ldb > (1L << 31) / 256))
+    return fail(c, ACE_E_UNSUPPORTED, "leading dimension too large for the BF16-split product");
   const int max_waves = sizeof(T) == 8 ? 8 : bf16_split ? 12 : 16;
   const int cu_waves = sizeof(T) == 8 ? 12 : bf16_split ? 12 : 16;
   CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
