@@ -928,14 +928,14 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
 // Line shape of the slab and plane passes: one thread per line or a quad per
 // line (far fewer registers: no spills for FP64 at large N, occupancy 4
 // instead of 1 for FP32 at N >= 64).  Defaults from timings on the MI355X:
-// FP32 slab pass quad only at N = 72, FP32 plane pass quad from N = 64, FP64
-// quad from N = 48.  The tuning knob ACE_TUNE_FFT_SHAPE overrides both
-// passes: 1 = thread, 4 = quad.
+// slab pass quad from N = 72 (FP32) or 64 (FP64), plane pass quad from
+// N = 64 (FP32) or 48 (FP64).  The tuning knob ACE_TUNE_FFT_SHAPE overrides
+// both passes: 1 = thread, 4 = quad.
 template <int N, typename T>
 bool use_quad(ace_ctx c, bool plane_pass) {
   if (c->fft_shape == 1) return false;
   if (c->fft_shape == 4) return true;
-  if (sizeof(T) == 8) return N >= 48;
+  if (sizeof(T) == 8) return plane_pass ? N >= 48 : N >= 64;
   return plane_pass ? N >= 64 : N >= 72;
 }
 

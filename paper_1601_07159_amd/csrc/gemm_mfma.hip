@@ -179,45 +179,55 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
   // Rolling pipeline over 8-point steps: the loads of step i + R - 1 are
   // issued before the MFMAs of step i, so R - 1 steps are always in flight.
   constexpr int R = sizeof(T) == 8 ? 2 : 4;
+  // Loads are unconditional (a conditional load makes the compiler wait for
+  // every load in flight at the join, which serialises the pipeline): a row
+  // outside the output reads row 0 (pa/pb are clamped) and is never stored; a
+  // point past the chunk reads the chunk's first point and is zeroed when
+  // used (kin).  K and kchunk are even, so k + 1 is in range with k.
   T a[R][2][4], b[R][2][4];
-  auto load = [&](T (&ar)[2][4], T (&br)[2][4], long k) {
-    const bool kin = k < kend;  // K and kchunk are even: k + 1 is in range too
+  bool kin[R];
+  auto load = [&](T (&ar)[2][4], T (&br)[2][4], bool& in, long k) {
+    in = k < kend;
+    const long kc = in ? k : kbeg;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      cx<T> x0 = {T(0), T(0)}, x1 = {T(0), T(0)}, y0 = {T(0), T(0)}, y1 = {T(0), T(0)};
-      if (kin && t.va[h]) {
-        x0 = t.pa[h][k];
-        x1 = t.pa[h][k + 1];
-      }
-      if (kin && t.vb[h]) {
-        y0 = t.pb[h][k];
-        y1 = t.pb[h][k + 1];
-      }
+      const cx<T> x0 = t.pa[h][kc], x1 = t.pa[h][kc + 1];
+      const cx<T> y0 = t.pb[h][kc], y1 = t.pb[h][kc + 1];
       ar[h][0] = x0.x; ar[h][1] = x0.y; ar[h][2] = x1.x; ar[h][3] = x1.y;
       br[h][0] = y0.x; br[h][1] = y0.y; br[h][2] = y1.x; br[h][3] = y1.y;
     }
   };
 #pragma unroll
-  for (int j = 0; j < R - 1; ++j) load(a[j], b[j], kbeg + 8 * j + 2 * kq);
-  for (long k0 = kbeg; k0 < kend; k0 += 8 * R) {
+  for (int j = 0; j < R - 1; ++j) load(a[j], b[j], kin[j], kbeg + 8 * j + 2 * kq);
+  // Tiles with all four 16-blocks inside the output (wave-uniform) take a
+  // branch-free loop that interleaves the eight accumulator chains; cut tiles
+  // skip the blocks outside.
+  auto run = [&](auto full) {
+    constexpr bool F = decltype(full)::value;
+    for (long k0 = kbeg; k0 < kend; k0 += 8 * R) {
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int nx = (j + R - 1) % R;
-      load(a[nx], b[nx], k0 + 8 * (j + R - 1) + 2 * kq);
+      for (int j = 0; j < R; ++j) {
+        const int nx = (j + R - 1) % R;
+        load(a[nx], b[nx], kin[nx], k0 + 8 * (j + R - 1) + 2 * kq);
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          if (!t.ba[x] || !t.bb[y]) continue;
+          for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const T bpp = (s & 1) ? -b[j][y][s ^ 1] : b[j][y][s ^ 1];
-            cre[x][y] = mfma4(a[j][x][s], b[j][y][s], cre[x][y]);
-            cim[x][y] = mfma4(a[j][x][s], bpp, cim[x][y]);
-          }
-        }
+            for (int y = 0; y < 2; ++y) {
+              if (!F && (!t.ba[x] || !t.bb[y])) continue;
+              const T av = kin[j] ? a[j][x][s] : T(0);
+              const T bpp = (s & 1) ? -b[j][y][s ^ 1] : b[j][y][s ^ 1];
+              cre[x][y] = mfma4(av, b[j][y][s], cre[x][y]);
+              cim[x][y] = mfma4(av, bpp, cim[x][y]);
+            }
+      }
     }
-  }
+  };
+  if (t.ba[1] && t.bb[1])
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -505,18 +515,21 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
     }
 }
 
-// Expansion product with all of C resident in LDS (n_a <= kNnResA): a
+// Expansion product with all of C resident in LDS (n_a <= ACAP): a
 // persistent grid of one 8-wave workgroup per CU stages its 16 NBB columns of
 // C once, then every wave walks 16 XB-row tiles of Y with a stride of the
 // whole grid, so the staging is paid once per CU instead of once per tile.
 // The grid-row loads run R steps (4 orbitals each) ahead of the MFMAs.
 constexpr int kNnResA = 80;
+// Larger resident capacity for FP32 accumulation with up to 64 columns per
+// workgroup: 256 orbitals x 64 columns x 8 bytes = 128 KiB of LDS.
+constexpr int kNnResA2 = 256;
 
 // upper: C is upper triangular (C[a][b] = 0 for a > b), so a step of four
 // orbitals past the last column of a 16-column block adds nothing to it and
 // its MFMAs are skipped (the triangular products xi = W L^{-H} and the
 // orthonormalisation's X R^{-1} do about 60% of the full work).
-template <typename TIn, typename TAcc, int NBB>
+template <typename TIn, typename TAcc, int NBB, int ACAP>
 __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__ A, long lda,
                                                      int na, const cx<double>* __restrict__ C,
                                                      int ldc, int nb, cx<TIn>* __restrict__ Y,
@@ -529,8 +542,8 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
   // spill the accumulators (hundreds of spills); there the zero blocks of an
   // upper-triangular C are multiplied instead.
   constexpr bool kSkip = NBB != 3 && NBB != 4;
-  __shared__ TAcc cs_re[kNnResA][NBC];
-  __shared__ TAcc cs_im[kNnResA][NBC];
+  __shared__ TAcc cs_re[ACAP][NBC];
+  __shared__ TAcc cs_im[ACAP][NBC];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const int b0 = blockIdx.y * NBC;
@@ -758,17 +771,22 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
   const int nbb = nb <= 16 ? 1 : nb <= 32 ? 2 : nb <= 48 ? 3 : nb <= 80 && nb > 64 ? 5 : 4;
   const dim3 block(256);
   const bool resident = na <= kNnResA;
+  const bool resident2 = !resident && na <= kNnResA2;
   const unsigned gy = (unsigned)((nb + 16 * nbb - 1) / (16 * nbb));
+#define ACE_NN_RES(NBBV, CAP)                                                                  \
+  {                                                                                            \
+    const long tiles = (K + 16 * NnShape<TAcc>::XB - 1) / (16 * NnShape<TAcc>::XB);            \
+    long gx = (tiles + 7) / 8;                                                                 \
+    const long cap = (256 + gy - 1) / gy;                                                      \
+    if (gx > cap) gx = cap;                                                                    \
+    return launch(c, name, k_nn_mfma_res<TIn, TAcc, NBBV, CAP>, dim3((unsigned)gx, gy),        \
+                  dim3(512), 0, A, lda, na, C, ldc, nb, Y, ldy, K, c_upper ? 1 : 0);           \
+  }
 #define ACE_NN(NBBV)                                                                           \
   case NBBV: {                                                                                 \
-    if (resident) {                                                                            \
-      const long tiles = (K + 16 * NnShape<TAcc>::XB - 1) / (16 * NnShape<TAcc>::XB);          \
-      long gx = (tiles + 7) / 8;                                                               \
-      const long cap = (256 + gy - 1) / gy;                                                    \
-      if (gx > cap) gx = cap;                                                                  \
-      return launch(c, name, k_nn_mfma_res<TIn, TAcc, NBBV>, dim3((unsigned)gx, gy), dim3(512), \
-                    0, A, lda, na, C, ldc, nb, Y, ldy, K, c_upper ? 1 : 0);                    \
-    }                                                                                          \
+    if (resident) ACE_NN_RES(NBBV, kNnResA)                                                    \
+    if constexpr (sizeof(TAcc) == 4 && NBBV <= 4)                                              \
+      if (resident2) ACE_NN_RES(NBBV, kNnResA2)                                                \
     const long rows = NnShape<TAcc>::ROWS;                                                    \
     const dim3 grid((unsigned)((K + rows - 1) / rows), gy);                                    \
     return launch(c, name, k_nn_mfma<TIn, TAcc, NBBV>, grid, block, 0, A, lda, na, C, ldc, nb, Y, \
@@ -782,6 +800,7 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
     ACE_NN(5)
   }
 #undef ACE_NN
+#undef ACE_NN_RES
   return fail(c, ACE_E_ARG, "internal: column block");
 }
 

@@ -67,6 +67,24 @@ def test_apply_matches_oracle(ace, case, prec):
     assert rel(to_np(Y), ref) <= tol(prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("nband", [81, 136, 256, 264])
+def test_apply_many_bands(ace, nband, prec):
+    # n_band past 80: the expansion keeps all of dV xi^H X in LDS up to 256
+    # orbitals in FP32, streams it in chunks beyond; full and cut 32-row tiles
+    # of the reduction (136 = 4 x 32 + 8)
+    n, L, nx = 16, 7.5, 37
+    print(f"apply prec={prec} nband={nband}", flush=True)
+    rng = np.random.default_rng(nband)
+    xi = (rng.standard_normal((nband, n, n, n)) + 1j * rng.standard_normal((nband, n, n, n))) * 0.05
+    X = rng.standard_normal((nx, n, n, n)) + 1j * rng.standard_normal((nx, n, n, n))
+    g = ogrid(n, L, "coulomb", 0.0)
+    gg = ggrid(n, L, "coulomb", 0.0)
+    Y = ace.apply(to_gpu(xi, prec), to_gpu(X, prec), gg, prec)
+    ref = O.ace_apply(xi, X, g)
+    assert rel(to_np(Y), ref) <= tol(prec)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_energy_both_forms_match_oracle(ace, case, prec):
     c = case
