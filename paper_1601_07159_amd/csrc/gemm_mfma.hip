@@ -566,14 +566,14 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
   for (long tile = (long)blockIdx.x * nwaves + wave; tile < ntiles;
        tile += (long)gridDim.x * nwaves) {
     const long rt0 = tile * 16 * XB;
-    acc_t yre[XB][NBB], yim[XB][NBB], ys[XB][sizeof(TAcc) == 8 ? NBB : 1];
+    acc_t yre[XB][NBB], yim[XB][NBB], ys[XB][NBB];
 #pragma unroll
     for (int x = 0; x < XB; ++x)
 #pragma unroll
       for (int y = 0; y < NBB; ++y) {
         yre[x][y] = acc_t{0, 0, 0, 0};
         yim[x][y] = acc_t{0, 0, 0, 0};
-        if constexpr (sizeof(TAcc) == 8) ys[x][y] = acc_t{0, 0, 0, 0};
+        ys[x][y] = acc_t{0, 0, 0, 0};
       }
     cx<TIn> buf[R][XB];
     // Unconditional loads from clamped addresses: an orbital past n_a meets
@@ -616,34 +616,25 @@ __global__ __launch_bounds__(512) void k_nn_mfma_res(const cx<TIn>* __restrict__
 #pragma unroll
             for (int x = 0; x < XB; ++x) {
               const TAcc xr = (TAcc)buf[j][x].x, xi = (TAcc)buf[j][x].y;
-              if constexpr (sizeof(TAcc) == 8) {
-                // three real products (Gauss): yre = P1 (x_re c_re), yim = P2
-                // (x_im c_im), ys = P3 ((x_re + x_im)(c_re + c_im));
-                // Re = P1 - P2, Im = P3 - P1 - P2 at the end
-                yre[x][y] = mfma4(xr, cr, yre[x][y]);
-                yim[x][y] = mfma4(xi, ci, yim[x][y]);
-                ys[x][y] = mfma4(xr + xi, cr + ci, ys[x][y]);
-              } else {
-                yre[x][y] = mfma4(xr, cr, yre[x][y]);
-                yre[x][y] = mfma4(xi, -ci, yre[x][y]);
-                yim[x][y] = mfma4(xr, ci, yim[x][y]);
-                yim[x][y] = mfma4(xi, cr, yim[x][y]);
-              }
+              // three real products (Gauss): yre = P1 (x_re c_re), yim = P2
+              // (x_im c_im), ys = P3 ((x_re + x_im)(c_re + c_im));
+              // Re = P1 - P2, Im = P3 - P1 - P2 at the end
+              yre[x][y] = mfma4(xr, cr, yre[x][y]);
+              yim[x][y] = mfma4(xi, ci, yim[x][y]);
+              ys[x][y] = mfma4(xr + xi, cr + ci, ys[x][y]);
             }
           }
         }
       }
     }
-    if constexpr (sizeof(TAcc) == 8) {
 #pragma unroll
-      for (int x = 0; x < XB; ++x)
+    for (int x = 0; x < XB; ++x)
 #pragma unroll
-        for (int y = 0; y < NBB; ++y) {
-          const acc_t p1 = yre[x][y], p2 = yim[x][y];
-          yre[x][y] = p1 - p2;
-          yim[x][y] = ys[x][y] - p1 - p2;
-        }
-    }
+      for (int y = 0; y < NBB; ++y) {
+        const acc_t p1 = yre[x][y], p2 = yim[x][y];
+        yre[x][y] = p1 - p2;
+        yim[x][y] = ys[x][y] - p1 - p2;
+      }
 #pragma unroll
     for (int x = 0; x < XB; ++x)
 #pragma unroll
