@@ -123,8 +123,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py: the ACE path runs on one GPU; --gpus above 1 is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -234,7 +234,7 @@ def main():
         f"events), stages {st_ms}")
 
     # dominant FFT-pass kernel and its roofline
-    # algorithmic HBM bytes per pair, in units of N_g * s (see DESIGN.md):
+    # algorithmic HBM bytes per pair, in units of N_g * s:
     #   pair_fwd_slab: write the slab spectra (inputs amortised over the pair block)
     #   plane_kernel:  read + write
     #   pencil_accum:  read (phi and W amortised over the pair block)

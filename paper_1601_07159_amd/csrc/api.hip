@@ -295,11 +295,11 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   int* info2 = (int*)ws_take(c, 256, &st);
   cx<T>* Y = (cx<T>*)ws_take(c, tmp, &st);
   if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
-  // round 1: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
+  // first pass: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
   ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true, true));
-  // round 2 on Y restores orthogonality lost to rounding in round 1
+  // the second pass on Y restores orthogonality lost to rounding in the first
   ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1, real));
   ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true, true));
