@@ -8,7 +8,10 @@
 // consecutive complex grid values (re0, im0, re1, im1) of its row; every real
 // becomes one K slot, so Re(conj(a) b) accumulates a_s b_s and Im(conj(a) b)
 // accumulates a_s b''_s with b'' = (im0, -re0, im1, -re1).  For the expansion
-// the K slots are (orbital a, re/im): Re y = ar cr - ai ci, Im y = ar ci + ai cr.
+// the K slots are orbitals: the streaming kernel forms Re y = ar cr - ai ci,
+// Im y = ar ci + ai cr (four real products), the resident one three real
+// products P1 = ar cr, P2 = ai ci, P3 = (ar + ai)(cr + ci) with Re y = P1 - P2,
+// Im y = P3 - P1 - P2 (Gauss).
 //
 // MFMA operand layout (16x16xK blocks): lane l supplies A[row l%16][k group
 // l/16] and B[k group l/16][col l%16]; the 16x16 result sits in 4 registers of
