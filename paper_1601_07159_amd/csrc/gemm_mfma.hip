@@ -421,10 +421,14 @@ struct NnShape {
   static constexpr int ROWS = 64 * XB;  // grid rows per workgroup
 };
 
+// upper: C is upper triangular, so chunks of orbitals past the workgroup's
+// last column are not staged or read, and steps past the last column of a
+// 16-column block skip its MFMAs.
 template <typename TIn, typename TAcc, int NBB>
 __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, long lda, int na,
                                                  const cx<double>* __restrict__ C, int ldc, int nb,
-                                                 cx<TIn>* __restrict__ Y, long ldy, long K) {
+                                                 cx<TIn>* __restrict__ Y, long ldy, long K,
+                                                 int upper) {
   typedef typename Acc4<TAcc>::type acc_t;
   constexpr int XB = NnShape<TAcc>::XB, KC = NnShape<TAcc>::KC;
   constexpr int NBC = 16 * NBB;
@@ -442,7 +446,8 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
       yre[x][y] = acc_t{0, 0, 0, 0};
       yim[x][y] = acc_t{0, 0, 0, 0};
     }
-  for (int ac = 0; ac < na; ac += KC) {
+  const int na_used = upper && b0 + NBC < na ? b0 + NBC : na;
+  for (int ac = 0; ac < na_used; ac += KC) {
     for (int e = threadIdx.x; e < KC * NBC; e += 256) {
       const int aa = e / NBC, bb = e - aa * NBC;
       TAcc vr = 0, vi = 0;
@@ -481,6 +486,7 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
         if (st >= steps) break;
 #pragma unroll
         for (int y = 0; y < NBB; ++y) {
+          if (upper && ac + 4 * st > b0 + 16 * y + 15) continue;  // wave-uniform
           const TAcc cr = cs_re[4 * st + kq][16 * y + r16];
           const TAcc ci = cs_im[4 * st + kq][16 * y + r16];
 #pragma unroll
@@ -784,7 +790,7 @@ static ace_status nn_dispatch(ace_ctx c, const char* name, const cx<TIn>* A, lon
     const long rows = NnShape<TAcc>::ROWS;                                                    \
     const dim3 grid((unsigned)((K + rows - 1) / rows), gy);                                    \
     return launch(c, name, k_nn_mfma<TIn, TAcc, NBBV>, grid, block, 0, A, lda, na, C, ldc, nb, Y, \
-                  ldy, K);                                                                     \
+                  ldy, K, c_upper ? 1 : 0);                                                    \
   }
   switch (nbb) {
     ACE_NN(1)
