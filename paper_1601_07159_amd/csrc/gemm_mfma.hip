@@ -133,14 +133,15 @@ __device__ __forceinline__ TileRows<T> tile_rows(const cx<T>* A, long lda, int n
 }
 
 // Hermitian mode (C = A^H A-like products whose lower triangle is the
-// conjugate of the upper one): the workgroup is one row of waves, wave w
-// taking the w-th tile on or above the diagonal, (0,0), (0,1), (1,1), (0,2),
-// ... (column-major over the upper triangle of tiles).
+// conjugate of the upper one): workgroups are rows of waves, wave w of
+// workgroup x taking tile number x * (waves per workgroup) + w on or above the
+// diagonal, in the order (0,0), (0,1), (1,1), (0,2), ... (column-major over
+// the upper triangle of tiles); a wave past the last tile has none.
 template <typename T>
 __device__ __forceinline__ TileRows<T> tile_rows_herm(const cx<T>* A, long lda, int na,
                                                       const cx<T>* B, long ldb, int nb, int r16) {
   TileRows<T> t;
-  int ty = 0, tx = (int)(threadIdx.x >> 6);
+  int ty = 0, tx = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   while (tx > ty) {
     tx -= ty + 1;
     ++ty;
@@ -692,18 +693,20 @@ static CnShape cn_shape(int na, int nb, long K, int max_waves, int cu_waves) {
   return s;
 }
 
-// Hermitian mode: one workgroup row of n_up = T(T+1)/2 waves (T tiles of 32
-// per side), as many workgroups per CU as cu_waves allows, one round.  Used
-// when n_up fits max_waves.
+// Hermitian mode: the n_up = T(T+1)/2 upper tiles (T tiles of 32 per side)
+// over gx workgroup rows of at most max_waves waves each, as many workgroups
+// per CU as cu_waves allows, one round.
 static bool herm_shape(int n, long K, int max_waves, int cu_waves, CnShape* s) {
   const int T = (n + 31) / 32, nup = T * (T + 1) / 2;
-  if (nup > max_waves) return false;
-  s->ta = nup;
+  const int gx = (nup + max_waves - 1) / max_waves;
+  const int w = (nup + gx - 1) / gx;
+  s->ta = w;
   s->tb = 1;
-  s->gx = s->gy = 1;
-  int per_cu = cu_waves / nup;
+  s->gx = gx;
+  s->gy = 1;
+  int per_cu = cu_waves / w;
   if (per_cu < 1) per_cu = 1;
-  long kchunk = (K + 256L * per_cu - 1) / (256L * per_cu);
+  long kchunk = (K * gx + 256L * per_cu - 1) / (256L * per_cu);
   kchunk = (kchunk + 63) / 64 * 64;
   if (kchunk < 64) kchunk = 64;
   s->kchunk = kchunk;

@@ -144,6 +144,35 @@ def test_config1_full_fp64(ace):
     assert abs(e - gold["E_X_coulomb"]) <= 1e-10 * abs(gold["E_X_coulomb"])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("nband", [100, 136, 200])
+def test_compress_hermitian_tiles_over_several_workgroups(ace, nband, prec):
+    # the upper 32 x 32 tiles of M = dV psi^H W (and of the Gram matrices)
+    # spread over more than one workgroup once they exceed one workgroup's
+    # waves (10, 15 and 28 tiles here: 12 waves per workgroup in BF16-split,
+    # 16 in FP32); cut tiles at 100 and 136
+    import torch
+    n, L, nocc = 16, 7.5, 40
+    print(f"compress herm prec={prec} nband={nband}", flush=True)
+    psi = synth.smooth_orbitals(n, L, nband, seed=5 * nband)
+    g = ogrid(n, L, "coulomb", 0.0)
+    W = O.build_W(psi[:nocc], psi, g)
+    _, Lc, xi = O.compress(psi, W, g)
+    gg = ggrid(n, L, "coulomb", 0.0)
+    info = torch.full((1,), -3, dtype=torch.int32, device="cuda")
+    xig, Lg = ace.compress(to_gpu(psi, prec), to_gpu(W, prec), gg, prec, want_L=True, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert rel(Lg.cpu().numpy(), Lc) <= tol(prec)
+    assert rel(to_np(xig), xi) <= tol(prec)
+    # the Gram matrices of the orthonormalisation, on a well-conditioned mix
+    rng = np.random.default_rng(nband)
+    mix = np.eye(nband) + 0.02 * rng.standard_normal((nband, nband))
+    X = (mix @ psi.reshape(nband, -1)).reshape(psi.shape)
+    Q = ace.orthonormalize(to_gpu(X, prec), gg, prec)
+    assert rel(to_np(Q), O.orthonormalize(X, g)) <= tol(prec)
+
+
 @pytest.mark.parametrize("nocc,nband", [(50, 81), (50, 88), (60, 96), (60, 100), (8, 520)])
 def test_compress_large_bands_both_factorisation_paths(ace, nocc, nband):
     # n_band <= 88 factorises in registers, larger n_band in global scratch with
