@@ -242,7 +242,9 @@ ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
  *                        (same pointer and ld), FFT only the pairs i <= j of the
  *                        occupied block and use u_ji = conj(u_ij); 0: all pairs
  *  ACE_TUNE_FFT_SHAPE    line FFTs of the slab and plane passes: 1 one thread
- *                        per line, 4 a lane quad per line, 0 (default) automatic
+ *                        per line, 4 a lane quad per line, 8 an octet of lanes
+ *                        per line (grids whose n is a multiple of 8 from 16;
+ *                        quads otherwise), 0 (default) automatic
  * They change speed only; results agree to rounding. */
 enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2,
        ACE_TUNE_FFT_SHAPE = 3 };

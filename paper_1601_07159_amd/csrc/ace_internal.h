@@ -39,7 +39,7 @@ struct ace_ctx_s {
   size_t pair_budget = 0;  // 0 = default
   long jblock = 0;         // band block of the build; 0 = automatic
   bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
-  int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread per line, 4 quad
+  int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread per line, 4 quad, 8 octet
   int num_cus = 256;
   std::string last_error;
   // profiling

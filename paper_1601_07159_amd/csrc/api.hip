@@ -401,7 +401,8 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
     case ACE_TUNE_JBLOCK: c->jblock = value; return ACE_OK;
     case ACE_TUNE_SYMMETRY: c->use_symmetry = value != 0; return ACE_OK;
     case ACE_TUNE_FFT_SHAPE:
-      if (value != 0 && value != 1 && value != 4) return fail(c, ACE_E_ARG, "fft shape 0, 1 or 4");
+      if (value != 0 && value != 1 && value != 4 && value != 8)
+        return fail(c, ACE_E_ARG, "fft shape 0, 1, 4 or 8");
       c->fft_shape = (int)value;
       return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");

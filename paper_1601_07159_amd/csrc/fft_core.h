@@ -443,4 +443,108 @@ __device__ __forceinline__ int quad_block_index(int k, int M, int h) {
   return k + M * (((h >> 1) | ((h & 1) << 1)));
 }
 
+// ---------------------------------------------------------------------------
+// Lines split over the 8 lanes of an octet (N = 8 M): at N = 72 a plane of
+// 72 lines is nine full waves (a quad split leaves half a wave idle and
+// carries 18 values per lane).  Layouts as for quads:
+//   decimated  lane h holds x[h + 8 m],              m = 0..M-1
+//   block      lane h holds X[k + M br3(h)],         k = 0..M-1,
+//              br3(h) = the three bits of h reversed
+// N = 8 x M: an M-point DFT per lane, twiddles exp(S 2 pi i h k / N), and an
+// 8-point DFT across the octet as three radix-2 exchanges (decimation in
+// frequency for d2b, in time for b2d): lanes h ^ 4 (DPP half-row mirror, then
+// quad reversal), h ^ 2 and h ^ 1 (quad permutations).  The lane-dependent
+// twiddles are read once per kernel (OctTw) for the forward sign; the inverse
+// uses their conjugates.
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane i <- lane 7 - i of its 8
+constexpr int kQuadRev = 0x1B;         // quad_perm [3,2,1,0]
+
+template <typename T>
+__device__ __forceinline__ cx<T> oct_swap4(cx<T> a) {  // value of lane h ^ 4
+  return quad_swap<kQuadRev>(quad_swap<kDppHalfMirror>(a));
+}
+
+template <int N, typename T>
+struct OctTw {
+  cx<T> w[N / 8];  // w[k] = exp(-2 pi i h k / N), k = 1..M-1
+  cx<T> w8;        // exp(-2 pi i (h & 3) / 8)
+};
+
+template <int N, typename T>
+__device__ __forceinline__ OctTw<N, T> oct_twiddles(int h) {
+  OctTw<N, T> t;
+  t.w[0] = {T(1), T(0)};
+#pragma unroll
+  for (int k = 1; k < N / 8; ++k) t.w[k] = root<N, -1, T>((h * k) % N);
+  t.w8 = root<8, -1, T>(h & 3);
+  return t;
+}
+
+template <int S, typename T>
+__device__ __forceinline__ cx<T> tw_sign(cx<T> w) {  // w for S = -1, conj(w) for S = +1
+  return S < 0 ? w : cx<T>{w.x, -w.y};
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_oct_d2b(cx<T>* v, int h, const OctTw<N, T>& tw) {
+  constexpr int M = N / 8;
+  static_assert(N % 8 == 0, "octet lines need N divisible by 8");
+  fft_line<M, S, T>(v);
+#pragma unroll
+  for (int k = 1; k < M; ++k) v[k] = cmul(v[k], tw_sign<S>(tw.w[k]));
+  const cx<T> w8 = tw_sign<S>(tw.w8);
+  const bool b2 = (h & 4) != 0, b1 = (h & 2) != 0, b0 = (h & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^4: (u, w) -> (u + w, (u - w) w8^(h & 3))
+    const cx<T> p = oct_swap4(v[k]);
+    v[k] = b2 ? cmul(csub(p, v[k]), w8) : cadd(v[k], p);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^2: (u, w) -> (u + w, (u - w) (S i)^(h & 1))
+    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    const cx<T> d = csub(p, v[k]);
+    v[k] = b1 ? (b0 ? mul_si<S>(d) : d) : cadd(v[k], p);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^1: (u, w) -> (u + w, u - w)
+    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    v[k] = b0 ? csub(p, v[k]) : cadd(v[k], p);
+  }
+}
+
+template <int N, int S, typename T>
+__device__ __forceinline__ void fft_oct_b2d(cx<T>* v, int h, const OctTw<N, T>& tw) {
+  constexpr int M = N / 8;
+  static_assert(N % 8 == 0, "octet lines need N divisible by 8");
+  const bool b2 = (h & 4) != 0, b1 = (h & 2) != 0, b0 = (h & 1) != 0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^1: sum and difference
+    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    v[k] = b0 ? csub(p, v[k]) : cadd(v[k], p);
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^2: the value of the bit-1 lane carries (S i)^(h & 1)
+    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    const cx<T> q = b1 ? v[k] : p, r = b1 ? p : v[k];
+    const cx<T> wq = b0 ? mul_si<S>(q) : q;
+    v[k] = b1 ? csub(r, wq) : cadd(r, wq);
+  }
+  const cx<T> w8 = tw_sign<S>(tw.w8);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {  // lanes h, h^4: the value of the bit-2 lane carries w8^(h & 3)
+    const cx<T> p = oct_swap4(v[k]);
+    const cx<T> q = b2 ? v[k] : p, r = b2 ? p : v[k];
+    const cx<T> wq = cmul(q, w8);
+    v[k] = b2 ? csub(r, wq) : cadd(r, wq);
+  }
+#pragma unroll
+  for (int k = 1; k < M; ++k) v[k] = cmul(v[k], tw_sign<S>(tw.w[k]));
+  fft_line<M, S, T>(v);
+}
+
+// block position of value k on lane h of an octet
+__device__ __forceinline__ int oct_block_index(int k, int M, int h) {
+  return k + M * (((h & 1) << 2) | (h & 2) | ((h >> 2) & 1));
+}
+
 }  // namespace ace

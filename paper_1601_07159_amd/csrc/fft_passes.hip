@@ -370,6 +370,107 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
   for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
 }
 
+// Octet forms of the slab and plane passes (N = 8 M lines over the 8 lanes of
+// an octet: 8N threads, line l = t / 8, lane h = t % 8).  LDS rows are kOctLd
+// apart with kOctLd = 2 (mod 16): a 16-lane phase of an 8-byte column access
+// (h + 8m) LD + l then touches 16 distinct banks; row accesses l LD + h + 8m
+// of two lines overlap in at most 6 of them.
+template <int N>
+constexpr int kOctLd = N + ((2 - N % 16) + 16) % 16;
+
+template <int N, typename T>
+__global__ __launch_bounds__(8 * N) void k_pair_fwd_slab_oct(const cx<T>* __restrict__ phi,
+                                                             long ldphi,
+                                                             const cx<T>* __restrict__ psi,
+                                                             long ldpsi, cx<T>* __restrict__ buf,
+                                                             int mode, int i0, int A, int j0,
+                                                             long p0, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kOctLd<N>;
+  constexpr int M = N / 8;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int x0 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)x0 * npairs);
+  int i, j;
+  pair_of(mode, i0, A, j0, p0, p, &i, &j);
+  const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
+  const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
+  const int t = threadIdx.x;
+  const int l = t >> 3, h = t & 7;
+  const int rr = t / N, cc = t - rr * N;  // element t + 8N q sits at row 8q + rr, column cc
+  const OctTw<N, T> tw = oct_twiddles<N, T>(h);
+  {
+    cx<T> va[M], vb[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) va[q] = a[(8 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) vb[q] = b[(8 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) s[(8 * q + rr) * LD + cc] = cmulc(va[q], vb[q]);
+  }
+  __syncthreads();
+  cx<T> v[M];
+  // axis 2: row l (read and rewritten by its own octet only: one wave, in order)
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 8 * m];
+  fft_oct_d2b<N, -1, T>(v, h, tw);
+#pragma unroll
+  for (int k = 0; k < M; ++k) s[l * LD + oct_block_index(k, M, h)] = v[k];
+  __syncthreads();
+  // axis 1: column l
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[(h + 8 * m) * LD + l];
+  fft_oct_d2b<N, -1, T>(v, h, tw);
+  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
+#pragma unroll
+  for (int k = 0; k < M; ++k) store_nt(&out[oct_block_index(k, M, h) * N], v[k]);
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(8 * N) void k_plane_kernel_oct(cx<T>* __restrict__ buf,
+                                                            const T* __restrict__ Kt, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kOctLd<N>;
+  constexpr int M = N / 8;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int k1 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)k1 * npairs);
+  const int t = threadIdx.x;
+  const int l = t >> 3, h = t & 7;
+  const OctTw<N, T> tw = oct_twiddles<N, T>(h);
+  cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
+  cx<T> v[M];
+  // axis 0 (column l of the plane): forward, kernel, inverse
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 8 * m) * NN + l];
+  fft_oct_d2b<N, -1, T>(v, h, tw);
+  const T* kcol = Kt + (size_t)k1 * N + l;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T kk = kcol[(size_t)oct_block_index(k, M, h) * NN];
+    v[k].x *= kk;
+    v[k].y *= kk;
+  }
+  fft_oct_b2d<N, +1, T>(v, h, tw);
+#pragma unroll
+  for (int m = 0; m < M; ++m) s[(h + 8 * m) * LD + l] = v[m];
+  __syncthreads();
+  // axis 2 (row l): inverse; the row is read and rewritten by its own octet
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 8 * m];
+  fft_oct_d2b<N, +1, T>(v, h, tw);
+#pragma unroll
+  for (int k = 0; k < M; ++k) s[l * LD + oct_block_index(k, M, h)] = v[k];
+  __syncthreads();
+  const int rr = t / N, cc = t - rr * N;
+#pragma unroll
+  for (int q = 0; q < M; ++q) plane[(size_t)(8 * q + rr) * NN + cc] = s[(8 * q + rr) * LD + cc];
+}
+
 // Pencil pass with accumulation: one thread per (x0, x2) pencil along axis 1,
 // 64 pencils per workgroup, one band per workgroup row of the grid.  Loops
 // over the orbitals i of the block: inverse FFT along axis 1, multiply by
@@ -934,15 +1035,31 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
 template <int N, typename T>
 bool use_quad(ace_ctx c, bool plane_pass) {
   if (c->fft_shape == 1) return false;
-  if (c->fft_shape == 4) return true;
+  if (c->fft_shape == 4 || c->fft_shape == 8) return true;
   if (sizeof(T) == 8) return plane_pass ? N >= 48 : N >= 64;
   return plane_pass ? N >= 64 : N >= 72;
+}
+
+// Octet lines (N a multiple of 8 from 16) only on request (knob value 8):
+// measured slower than the defaults at every size (at N = 72 FP32 the slab
+// pass 8.1 vs 5.6 ms and the plane pass 7.5 vs 6.2 ms for 64 x 80 pairs),
+// as the third exchange, the per-lane twiddles and the 64-byte row segments
+// of the plane's column loads cost more than the full waves gain.
+template <int N, typename T>
+constexpr bool kOctOk = N % 8 == 0 && N >= 16;
+template <int N, typename T>
+bool use_oct(ace_ctx c) {
+  return kOctOk<N, T> && c->fft_shape == 8;
 }
 
 template <int N, typename T>
 ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx<T>* psi,
                     long ldpsi, cx<T>* buf, int mode, int i0, int A, int j0, long p0, int np) {
   const dim3 grid(xcd_pad((long)N * np));
+  if constexpr (kOctOk<N, T>)
+    if (use_oct<N, T>(c))
+      return launch(c, "pair_fwd_slab", k_pair_fwd_slab_oct<N, T>, grid, dim3(8 * N), 0, phi,
+                    ldphi, psi, ldpsi, buf, mode, i0, A, j0, p0, np);
   if (quad)
     return launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, grid, dim3(4 * N), 0, phi, ldphi, psi,
                   ldpsi, buf, mode, i0, A, j0, p0, np);
@@ -955,6 +1072,10 @@ ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx
 template <int N, typename T>
 ace_status plane(ace_ctx c, bool quad, cx<T>* buf, const T* Kt, int np) {
   const dim3 grid(xcd_pad((long)N * np));
+  if constexpr (kOctOk<N, T>)
+    if (use_oct<N, T>(c))
+      return launch(c, "plane_kernel", k_plane_kernel_oct<N, T>, grid, dim3(8 * N), 0, buf, Kt,
+                    np);
   if (quad)
     return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, Kt, np);
   constexpr int P = t1_group<N, T>(80 * 1024);

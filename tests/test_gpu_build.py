@@ -40,6 +40,33 @@ def test_build_W_matches_oracle(ace, prec, n, L, nocc, nband, kind, mu, g0):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [1, 4, 8])
+@pytest.mark.parametrize("n,L", [(12, 5.0), (16, 6.0), (24, 10.0), (32, 13.0), (40, 17.0),
+                                 (48, 20.5), (64, 27.0), (72, 30.8)])
+def test_build_W_line_shapes(ace, prec, shape, n, L):
+    # every line form of the slab and plane passes (one thread, a quad or an
+    # octet of lanes per line; octets need n divisible by 8 from 16, quads
+    # stand in below) on the symmetric merged path and the rectangle path
+    print(f"build_W shape={shape} prec={prec} n={n}", flush=True)
+    nocc, nband = 2, 3
+    psi = synth.smooth_orbitals(n, L, nband, seed=7 * n + shape)
+    g = ogrid(n, L, "erfc", 0.3)
+    gg = ggrid(n, L, "erfc", 0.3)
+    ref = O.build_W(psi[:nocc], psi, g)
+    ctx = ace.Context()
+    ctx.set_tuning("fft_shape", shape)
+    x = to_gpu(psi, prec)
+    W_sym = to_np(ctx.build_W(x[:nocc], x, gg, prec))
+    W_rect = to_np(ctx.build_W(x[:nocc].clone(), x, gg, prec))
+    e_dir = float(ctx.exchange_energy(x[:nocc], gg, prec).item())
+    ctx.close()
+    assert rel(W_sym.reshape(ref.shape), ref) <= tol(prec)
+    assert rel(W_rect.reshape(ref.shape), ref) <= tol(prec)
+    e_ref = O.exchange_energy_direct(psi[:nocc], g)
+    assert abs(e_dir - e_ref) <= tol(prec) * abs(e_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_build_W_planewave_closed_form(ace, prec):
     n, L = 16, 7.0
     occ = [(0, 0, 0), (1, 0, 0), (0, 2, -1), (-3, 1, 4)]
