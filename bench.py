@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--pair-budget", type=int, default=0,
                     help="bytes of pair spectra in flight (0 = library default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="cfg4: skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -401,6 +403,16 @@ def run_batched(args, cfg):
     del orbs
     ctx = ace.Context(0)
     nbr = 4
+    tuned = {}
+    if not args.no_autotune:
+        # pair-batch width, band block and FFT line shape per grid size, tuned
+        # on that size's median instance (outside the timed region)
+        for n in sorted({sp["n"] for sp in specs}):
+            same = sorted((sp for sp in specs if sp["n"] == n), key=lambda sp: sp["nocc"])
+            med = same[len(same) // 2]
+            r = ctx.autotune(ace.Grid.cubic(n, med["L"]), "fp32", med["nocc"], med["nband"])
+            tuned[n] = {k: r[k] for k in ("pair_budget", "jblock", "fft_shape")}
+            log(f"bench: cfg4: autotuned n={n}: {tuned[n]} ({r['ms']:.2f} ms per build)")
     ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32", n_branches=nbr),
                      args.steps, args.warmup) * 1e3
     bad = [k for k, d in enumerate(insts) if int(d["info"].item()) != 0]
@@ -409,7 +421,8 @@ def run_batched(args, cfg):
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": fft_bytes, "avg_launch_ms": round(ms, 4)}
-    extra = {"instances": len(insts), "branches": nbr, "pairs_per_step": pairs,
+    extra = {"instances": len(insts), "branches": nbr, "autotuned": tuned,
+             "pairs_per_step": pairs,
              "transformed_pairs_per_step": transformed, "failed_cholesky": bad,
              "fft_roofline_ms": fft_bytes / (HBM_PEAK_GBS * 1e9) * 1e3}
     config = {"workload": f"cfg4: {cfg['desc']}", "precision": "fp32",

@@ -203,19 +203,23 @@ ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_i
                              int n_branches);
 
 /*
- * Autotuner of the build's blocking for one grid size and precision: times
- * ace_build_W on scratch orbitals (n_occ of n_band, allocated and freed here,
- * so this call allocates and synchronises) over candidate pair budgets (the
- * number of pair spectra in flight) and band blocks, and keeps the fastest in
- * the context; later builds of that grid size use it unless the explicit knobs
- * are set.  cache_path (nullable): the result is appended as a text line
- * "n element_bytes budget jblock".  Outputs (nullable): the choice and its
- * time per build in ms.
+ * Autotuner of the build for one grid size and precision: times ace_build_W on
+ * scratch orbitals (n_occ of n_band, allocated and freed here, so this call
+ * allocates and synchronises) over candidate pair budgets (the number of pair
+ * spectra in flight) and band blocks, then, at the fastest of those, over the
+ * line shapes of the FFT passes (ACE_TUNE_FFT_SHAPE values 1, 4 and 8), and
+ * keeps the fastest in the context; later builds of that grid size and
+ * element size use it where the explicit knobs are not set.  cache_path
+ * (nullable): the result is appended as a text line "n element_bytes budget
+ * jblock shape".  Outputs (nullable): the choice (shape 0 = the defaults) and
+ * its time per build in ms.  Complex precisions only (ACE_E_UNSUPPORTED for the
+ * real ones).
  */
 ace_status ace_autotune(ace_ctx ctx, const ace_grid* grid, ace_prec prec, int n_occ, int n_band,
                         const char* cache_path, long* best_budget, long* best_jblock,
-                        double* best_ms);
-/* Load tuning results written by ace_autotune (later lines win). */
+                        int* best_shape, double* best_ms);
+/* Load tuning results written by ace_autotune (later lines win; a line
+ * without the shape field reads as shape 0). */
 ace_status ace_tune_load(ace_ctx ctx, const char* cache_path);
 
 /* Grid sizes n (per axis) compiled into this library; returns how many were

@@ -56,7 +56,7 @@ _PROTOS = {
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
     "ace_build_batched": (_i, [_vp, _i, _i, ctypes.POINTER(AceInstance), _i]),
     "ace_autotune": (_i, [_vp, _gp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_l),
-                          ctypes.POINTER(_l), ctypes.POINTER(_d)]),
+                          ctypes.POINTER(_l), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
     "ace_tune_load": (_i, [_vp, ctypes.c_char_p]),
     "ace_profile_enable": (_i, [_vp, _i]),
     "ace_profile_reset": (_i, [_vp]),

@@ -301,15 +301,17 @@ class Context:
         self._check(self._lib.ace_build_batched(self._h, p, len(instances), arr, int(n_branches)))
 
     def autotune(self, grid: Grid, prec, n_occ: int, n_band: int, cache_path=None) -> dict:
-        """Time the build over pair budgets and band blocks; keep the fastest."""
+        """Time the build over pair budgets, band blocks and FFT line shapes; keep
+        the fastest for this grid size (ace_autotune)."""
         g = grid.as_c()
-        bud, jb, ms = ctypes.c_long(), ctypes.c_long(), ctypes.c_double()
+        bud, jb, sh, ms = ctypes.c_long(), ctypes.c_long(), ctypes.c_int(), ctypes.c_double()
         self._bind_stream()
         self._check(self._lib.ace_autotune(
             self._h, ctypes.byref(g), _prec(prec), int(n_occ), int(n_band),
             cache_path.encode() if cache_path else None, ctypes.byref(bud), ctypes.byref(jb),
-            ctypes.byref(ms)))
-        return {"pair_budget": bud.value, "jblock": jb.value, "ms": ms.value}
+            ctypes.byref(sh), ctypes.byref(ms)))
+        return {"pair_budget": bud.value, "jblock": jb.value, "fft_shape": sh.value,
+                "ms": ms.value}
 
     def tune_load(self, cache_path: str):
         self._check(self._lib.ace_tune_load(self._h, cache_path.encode()))

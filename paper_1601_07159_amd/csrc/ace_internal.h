@@ -22,14 +22,18 @@ struct ace_ctx_s {
   char* sub_base = nullptr;
   size_t sub_bytes = 0;
   // batched build: branch streams, fork/join events, cached graph
-  // autotuned build blocking per (grid size, element bytes): {pair budget, band block}
+  // autotuned build settings per (grid size, element bytes): {pair budget, band
+  // block, line shape of the slab and plane passes (0 = defaults)}; tune_gen
+  // counts changes (it keys the batched build's cached graph)
   struct Tuned {
     int n;
     int eb;
     long budget;
     long jblock;
+    int shape;
   };
   std::vector<Tuned> tuned;
+  unsigned tune_gen = 0;
   hipStream_t capture_stream = nullptr;
   std::vector<hipStream_t> branch_streams;
   std::vector<hipEvent_t> branch_events;

@@ -68,6 +68,7 @@ std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_i
   const int symm = c->use_symmetry ? 1 : 0;
   std::memcpy(t + 48, &symm, sizeof symm);
   std::memcpy(t + 52, &c->fft_shape, sizeof c->fft_shape);
+  std::memcpy(t + 56, &c->tune_gen, sizeof c->tune_gen);
   return k;
 }
 

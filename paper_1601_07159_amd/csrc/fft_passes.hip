@@ -1031,11 +1031,20 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
 // instead of 1 for FP32 at N >= 64).  Defaults from timings on the MI355X:
 // slab pass quad from N = 72 (FP32) or 64 (FP64), plane pass quad from
 // N = 64 (FP32) or 48 (FP64).  The tuning knob ACE_TUNE_FFT_SHAPE overrides
-// both passes: 1 = thread, 4 = quad.
+// both passes (1 = thread, 4 = quad, 8 = octet), else an autotuned shape for
+// this grid size and element size.
+int line_shape(ace_ctx c, int n, int eb) {
+  if (c->fft_shape) return c->fft_shape;
+  for (const auto& t : c->tuned)
+    if (t.n == n && t.eb == eb && t.shape) return t.shape;
+  return 0;
+}
+
 template <int N, typename T>
 bool use_quad(ace_ctx c, bool plane_pass) {
-  if (c->fft_shape == 1) return false;
-  if (c->fft_shape == 4 || c->fft_shape == 8) return true;
+  const int sh = line_shape(c, N, (int)sizeof(cx<T>));
+  if (sh == 1) return false;
+  if (sh == 4 || sh == 8) return true;
   if (sizeof(T) == 8) return plane_pass ? N >= 48 : N >= 64;
   return plane_pass ? N >= 64 : N >= 72;
 }
@@ -1049,7 +1058,7 @@ template <int N, typename T>
 constexpr bool kOctOk = N % 8 == 0 && N >= 16;
 template <int N, typename T>
 bool use_oct(ace_ctx c) {
-  return kOctOk<N, T> && c->fft_shape == 8;
+  return kOctOk<N, T> && line_shape(c, N, (int)sizeof(cx<T>)) == 8;
 }
 
 template <int N, typename T>

@@ -1,8 +1,10 @@
-// Autotuner of the build's blocking: for one grid size and precision it times
-// the build over candidate pair budgets (how many pair spectra are in flight,
-// i.e. the pair-batch width) and band blocks on scratch orbitals, keeps the
+// Autotuner of the build: for one grid size and precision it times the build
+// on scratch orbitals over candidate pair budgets (how many pair spectra are in
+// flight, i.e. the pair-batch width) and band blocks, then, at the fastest of
+// those, over the line shapes of the slab and plane FFT passes (one thread,
+// a quad or an octet of lanes per line; the tile of a line FFT); keeps the
 // fastest in the context, and optionally appends it to a text cache file
-// ("n elem_bytes budget jblock" per line) that ace_tune_load reads back.
+// ("n elem_bytes budget jblock shape" per line) that ace_tune_load reads back.
 #include <cstdio>
 #include <vector>
 
@@ -26,14 +28,16 @@ __global__ __launch_bounds__(256) void k_fill_scratch(cx<T>* x, int n, int count
   x[idx] = {T(cos(ph) * (1.0 + 0.1 * b)), T(sin(ph))};
 }
 
-void upsert(ace_ctx c, int n, int eb, long budget, long jblock) {
+void upsert(ace_ctx c, int n, int eb, long budget, long jblock, int shape) {
+  ++c->tune_gen;
   for (auto& t : c->tuned)
     if (t.n == n && t.eb == eb) {
       t.budget = budget;
       t.jblock = jblock;
+      t.shape = shape;
       return;
     }
-  c->tuned.push_back({n, eb, budget, jblock});
+  c->tuned.push_back({n, eb, budget, jblock, shape});
 }
 
 }  // namespace
@@ -43,7 +47,7 @@ using namespace ace;
 
 ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec prec, int n_occ,
                                    int n_band, const char* cache_path, long* best_budget,
-                                   long* best_jblock, double* best_ms) {
+                                   long* best_jblock, int* best_shape, double* best_ms) {
   if (!c) return ACE_E_ARG;
   GridInfo g;
   ACE_TRY(check_grid(c, grid, prec, &g));
@@ -69,6 +73,7 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
                                (cx<float>*)psi, g.n, n_band);
   const size_t save_budget = c->pair_budget;
   const long save_jblock = c->jblock;
+  const int save_shape = c->fft_shape;
   const bool save_prof = c->profiling;
   c->profiling = false;
   const long budgets[] = {256L << 20, 512L << 20, 1L << 30, 2L << 30, 4L << 30, 8L << 30};
@@ -79,7 +84,30 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
   hipEventCreate(&e1);
   double best = 1e300;
   long bb = 0, bj = 0;
+  int bs = 0;
   const size_t pair_bytes = (size_t)g.ng * eb;
+  auto run = [&]() {
+    return prec == ACE_FP64
+               ? build_W_impl<double>(c, g, (const cx<double>*)psi, n_occ, g.ng,
+                                      (const cx<double>*)psi, n_band, g.ng, (cx<double>*)W, g.ng,
+                                      1.0)
+               : build_W_impl<float>(c, g, (const cx<float>*)psi, n_occ, g.ng,
+                                     (const cx<float>*)psi, n_band, g.ng, (cx<float>*)W, g.ng,
+                                     1.0);
+  };
+  // time of one build (mean of three after a warm-up that also grows the
+  // workspace), or a negative value on failure
+  auto time_build = [&]() -> double {
+    if ((st = run()) != ACE_OK) return -1.0;
+    float ms = 0.f;
+    hipEventRecord(e0, c->stream);
+    for (int r = 0; r < 3 && st == ACE_OK; ++r) st = run();
+    hipEventRecord(e1, c->stream);
+    hipEventSynchronize(e1);
+    hipEventElapsedTime(&ms, e0, e1);
+    return st == ACE_OK ? ms / 3.0 : -1.0;
+  };
+  c->fft_shape = 0;
   for (long bud : budgets) {
     if (st != ACE_OK) break;
     // skip budgets that change nothing: larger than every pair at once
@@ -87,48 +115,51 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
     for (long jb : jblocks) {
       c->pair_budget = (size_t)bud;
       c->jblock = jb;
-      auto run = [&]() {
-        return prec == ACE_FP64
-                   ? build_W_impl<double>(c, g, (const cx<double>*)psi, n_occ, g.ng,
-                                          (const cx<double>*)psi, n_band, g.ng, (cx<double>*)W,
-                                          g.ng, 1.0)
-                   : build_W_impl<float>(c, g, (const cx<float>*)psi, n_occ, g.ng,
-                                         (const cx<float>*)psi, n_band, g.ng, (cx<float>*)W, g.ng,
-                                         1.0);
-      };
-      if ((st = run()) != ACE_OK) break;  // warm-up (and workspace growth)
-      float ms = 0.f;
-      hipEventRecord(e0, c->stream);
-      for (int r = 0; r < 3 && st == ACE_OK; ++r) st = run();
-      hipEventRecord(e1, c->stream);
-      hipEventSynchronize(e1);
-      hipEventElapsedTime(&ms, e0, e1);
-      if (st == ACE_OK && ms / 3.0 < best) {
-        best = ms / 3.0;
+      const double ms = time_build();
+      if (ms < 0) break;
+      if (ms < best) {
+        best = ms;
         bb = bud;
         bj = jb;
       }
+    }
+  }
+  // line shapes at the chosen blocking (0, the defaults, was timed above)
+  const int shapes[] = {1, 4, 8};
+  c->pair_budget = (size_t)bb;
+  c->jblock = bj;
+  for (int sh : shapes) {
+    if (st != ACE_OK) break;
+    if (sh == 8 && (g.n % 8 != 0 || g.n < 16)) continue;
+    c->fft_shape = sh;
+    const double ms = time_build();
+    if (ms < 0) break;
+    if (ms < best) {
+      best = ms;
+      bs = sh;
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->pair_budget = save_budget;
   c->jblock = save_jblock;
+  c->fft_shape = save_shape;
   c->profiling = save_prof;
   hipStreamSynchronize(c->stream);
   hipFree(psi);
   hipFree(W);
   if (st != ACE_OK) return st;
-  upsert(c, g.n, (int)eb, bb, bj);
+  upsert(c, g.n, (int)eb, bb, bj, bs);
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%d %d %ld %ld\n", g.n, (int)eb, bb, bj);
+      fprintf(f, "%d %d %ld %ld %d\n", g.n, (int)eb, bb, bj, bs);
       fclose(f);
     }
   }
   if (best_budget) *best_budget = bb;
   if (best_jblock) *best_jblock = bj;
+  if (best_shape) *best_shape = bs;
   if (best_ms) *best_ms = best;
   return ACE_OK;
 }
@@ -137,10 +168,18 @@ ACE_EXPORT ace_status ace_tune_load(ace_ctx c, const char* cache_path) {
   if (!c || !cache_path) return ACE_E_ARG;
   FILE* f = fopen(cache_path, "r");
   if (!f) return fail(c, ACE_E_ARG, "cannot open tuning cache");
-  int n, eb;
-  long bud, jb;
-  while (fscanf(f, "%d %d %ld %ld", &n, &eb, &bud, &jb) == 4)
-    if (n > 0 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0) upsert(c, n, eb, bud, jb);
+  // one setting per line: "n eb budget jblock [shape]" (shape 0 when absent)
+  char line[256];
+  while (fgets(line, sizeof line, f)) {
+    int n, eb, shape = 0;
+    long bud, jb;
+    const int got = sscanf(line, "%d %d %ld %ld %d", &n, &eb, &bud, &jb, &shape);
+    if (got < 4) continue;
+    if (got == 4) shape = 0;
+    if (n > 0 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0 &&
+        (shape == 0 || shape == 1 || shape == 4 || shape == 8))
+      upsert(c, n, eb, bud, jb, shape);
+  }
   fclose(f);
   return ACE_OK;
 }
