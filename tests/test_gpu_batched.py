@@ -116,3 +116,31 @@ def test_config4_48_instances(ace):
         for c, j in enumerate(cols):
             assert rel(Wn[j], ref[c]) <= 1e-5
     ctx.close()
+
+
+def test_batched_recaptures_after_tuning(ace, tmp_path):
+    # a new autotuned setting (here a line shape and a pair budget read from a
+    # cache file) changes the build's launches; the cached graph must be
+    # captured again, so the batch still equals the single calls under the new
+    # setting, bit for bit
+    import torch
+    insts, host = _make(ace, "fp32", SMALL[:3], 80)
+    ctx = ace.Context()
+    ctx.build_batched(insts, "fp32", n_branches=2)          # capture
+    torch.cuda.synchronize()
+    before = [d["W"].clone() for d in insts]
+    cache = tmp_path / "tune.txt"
+    cache.write_text("".join(f"{n} 8 {1 << 20} 0 4\n" for n in (16, 24, 32)))
+    ctx.tune_load(str(cache))                                # quad lines, 1 MiB budget
+    ctx.build_batched(insts, "fp32", n_branches=2)          # must not replay the old graph
+    torch.cuda.synchronize()
+    changed = 0
+    for d, (psi, og, nocc), old in zip(insts, host, before):
+        W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], "fp32")
+        assert torch.equal(W1, d["W"])
+        changed += int(not torch.equal(old, d["W"]))
+        ref = O.build_W(psi[:nocc], psi, og)
+        assert rel(to_np(d["W"]), ref) <= 1e-5
+        assert rel(to_np(old), ref) <= 1e-5
+    assert changed > 0  # the new setting rounds differently, so a stale graph would show
+    ctx.close()
