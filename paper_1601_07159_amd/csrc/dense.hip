@@ -43,6 +43,19 @@ __device__ __forceinline__ cx<double> cmulcj_d(cx<double> a, cx<double> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
+// value of lane J of this lane's quad (DPP quad_perm [J,J,J,J])
+template <int J>
+__device__ __forceinline__ double quad_bcast(double v) {
+  const long long u = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), J * 0x55, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), J * 0x55, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int J>
+__device__ __forceinline__ cx<double> quad_bcast(cx<double> v) {
+  return {quad_bcast<J>(v.x), quad_bcast<J>(v.y)};
+}
+
 __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, int n, double s,
                                               cx<double>* A, int lda, cx<double>* T,
                                               cx<double>* __restrict__ Lout,
@@ -279,43 +292,61 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
         Lr[r][k] = A[(ri + r) + (size_t)k * lda];
       }
       __syncthreads();
-      // one thread per column: T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]
-      // for all r of the block row, then X[ri + r][col] = -sum_{q <= r} X_ii[r][q] T[q][col]
-      for (int col = t; col < ri; col += nt) {
-        cx<double> acc[NB];
+      // four threads (a lane quad) per column, each with four rows r of the
+      // block row: T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]; the
+      // quad then shares its T values through DPP broadcasts and each thread
+      // forms X[ri + r][col] = -sum_{q <= r} X_ii[r][q] T[q][col] for its rows.
+      // (All four lanes of a quad take the same trip counts: 4 ri and the
+      // workgroup size are multiples of 4.)
+      constexpr int RQ = NB / 4;
+      for (int e = t; e < 4 * ri; e += nt) {
+        const int col = e >> 2, g = e & 3;
+        cx<double> acc[RQ];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) acc[r] = {0.0, 0.0};
-        const int cb_end = (col / NB + 1) * NB;  // X[k][col] for k < cb_end: diagonal block
-        for (int k = col; k < ri; ++k) {
-          // the diagonal block holds X in place; finished blocks hold conj(X) in the
-          // upper triangle of A
-          cx<double> x;
-          if (k < cb_end) {
-            x = A[k + (size_t)col * lda];
-          } else {
-            const cx<double> xc = A[col + (size_t)k * lda];
-            x = {xc.x, -xc.y};
-          }
+        for (int r = 0; r < RQ; ++r) acc[r] = {0.0, 0.0};
+        const int cb_end = (col / NB + 1) * NB;  // <= ri: X[k][col] for k < cb_end is diagonal
+        for (int k = col; k < cb_end; ++k) {   // the diagonal block holds X in place
+          const cx<double> x = A[k + (size_t)col * lda];
 #pragma unroll
-          for (int r = 0; r < NB; ++r) {
-            const cx<double> u = cmul_d(Lr[r][k], x);
+          for (int r = 0; r < RQ; ++r) {
+            const cx<double> u = cmul_d(Lr[RQ * g + r][k], x);
             acc[r].x += u.x;
             acc[r].y += u.y;
           }
         }
+        for (int k = cb_end; k < ri; ++k) {  // finished blocks hold conj(X) above the diagonal
+          const cx<double> xc = A[col + (size_t)k * lda];
+          const cx<double> x = {xc.x, -xc.y};
 #pragma unroll
-        for (int r = 0; r < NB; ++r) {
-          if (r >= ni) break;
+          for (int r = 0; r < RQ; ++r) {
+            const cx<double> u = cmul_d(Lr[RQ * g + r][k], x);
+            acc[r].x += u.x;
+            acc[r].y += u.y;
+          }
+        }
+        cx<double> T[NB];
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) {
+          T[r] = quad_bcast<0>(acc[r]);
+          T[RQ + r] = quad_bcast<1>(acc[r]);
+          T[2 * RQ + r] = quad_bcast<2>(acc[r]);
+          T[3 * RQ + r] = quad_bcast<3>(acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) {
+          const int rr = RQ * g + r;
+          if (rr >= ni) break;
           cx<double> sm = {0.0, 0.0};
 #pragma unroll
-          for (int q = 0; q <= r; ++q) {
-            const cx<double> u = cmul_d(Lr[r][ri + q], acc[q]);
+          for (int q = 0; q < NB; ++q) {
+            if (q > rr) break;
+            const cx<double> u = cmul_d(Lr[rr][ri + q], T[q]);
             sm.x += u.x;
             sm.y += u.y;
           }
-          const cx<double> xc = {-sm.x, sm.y};  // conj(X[ri + r][col])
-          A[col + (size_t)(ri + r) * lda] = xc;
-          C[col + (size_t)(ri + r) * n] = xc;
+          const cx<double> xc = {-sm.x, sm.y};  // conj(X[ri + rr][col])
+          A[col + (size_t)(ri + rr) * lda] = xc;
+          C[col + (size_t)(ri + rr) * n] = xc;
         }
       }
       __syncthreads();
