@@ -150,15 +150,33 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
         const int c = e / R, r = e - c * R;
         if (r >= c) A[(kb + r) + (size_t)(kb + c) * lda] = P[c][r];
       }
-      for (int j = kb + nb + wave; j < n; j += nw)
-        for (int i = j + lane; i < n; i += 64) {
-          cx<double> acc = A[i + (size_t)j * lda];
-          for (int c = 0; c < nb; ++c) {
-            const cx<double> u = cmulcj_d(P[c][i - kb], P[c][j - kb]);
-            acc.x -= u.x;
-            acc.y -= u.y;
+      // four columns jb..jb+3 per wave and lane row i: P[c][i] is read once for
+      // the four (the P[c][j] are wave-uniform broadcasts).  Loads are
+      // unconditional from clamped columns; entries above the diagonal or past
+      // n are computed on scratch values and not stored.
+      for (int jb = kb + nb + 4 * wave; jb < n; jb += 4 * nw)
+        for (int i = jb + lane; i < n; i += 64) {
+          cx<double> acc[4];
+          int jq[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            jq[q] = jb + q < n ? jb + q : n - 1;
+            acc[q] = A[i + (size_t)jq[q] * lda];
           }
-          A[i + (size_t)j * lda] = acc;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            if (c >= nb) break;
+            const cx<double> pi = P[c][i - kb];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const cx<double> u = cmulcj_d(pi, P[c][jq[q] - kb]);
+              acc[q].x -= u.x;
+              acc[q].y -= u.y;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (jb + q < n && i >= jb + q) A[i + (size_t)(jb + q) * lda] = acc[q];
         }
       __syncthreads();
       continue;
