@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void k_nn_mfma(const cx<TIn>* __restrict__ A, 
 // persistent grid of one 8-wave workgroup per CU stages its 16 NBB columns of
 // C once, then every wave walks 16 XB-row tiles of Y with a stride of the
 // whole grid, so the staging is paid once per CU instead of once per tile.
-// The grid-row loads run R steps (4 orbitals each) ahead of the MFMAs.
+// The grid-row loads run R - 1 steps (4 orbitals each) ahead of the MFMAs.
 constexpr int kNnResA = 80;
 // Larger resident capacity for FP32 accumulation with up to 64 columns per
 // workgroup: 256 orbitals x 64 columns x 8 bytes = 128 KiB of LDS.
