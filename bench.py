@@ -30,9 +30,11 @@ WORKLOADS = {
                  desc="48^3 grid, L=20.5 bohr, N_occ=64, N_band=80, complex64 FFTs, "
                       "BF16-split M, FP64 Cholesky/TRSM, Coulomb"),
     "cfg3": dict(n=72, L=30.8, nocc=216, nband=256, nx=256, kind="erfc", mu=0.106, prec="fp32",
-                 applies=20,
+                 applies=20, x_seeds=list(range(100, 120)),
+                 golden="tests/golden/smooth72_erfc_seed0.json",
                  desc="72^3 grid, L=30.8 bohr, N_occ=216, N_band=256, FP32 FFTs, FP64 "
-                      "compression, erfc mu=0.106, 20 applications of V_ACE per build"),
+                      "compression, erfc mu=0.106, 20 applications of V_ACE per build on "
+                      "X_t = generator(seed 100 + t)"),
     "cfg2r": dict(n=48, L=20.5, nocc=64, nband=80, nx=80, kind="coulomb", mu=0.0, prec="real32",
                   desc="48^3 grid, L=20.5 bohr, N_occ=64, N_band=80, real orbitals (Gamma "
                        "point): two pair charges per complex64 FFT, BF16-split M, FP64 "
@@ -79,32 +81,88 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, seconds=10.0):
-    """Time the FP64 oracle's pair solves on a bounded sample of the workload:
-    whole columns j of W (each column = N_occ pair solves), as many as fit in
-    about `seconds` of single-threaded CPU work."""
-    import numpy as np
-
+def _oracle_inputs(cfg):
     import oracle as O
     from paper_1601_07159_amd import synth
     if cfg.get("prec", "").startswith("real"):
         psi = synth.real_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
     else:
         psi = synth.smooth_orbitals(cfg["n"], cfg["L"], cfg["nband"], seed=0)
+    return psi, O.Grid.cubic(cfg["n"], cfg["L"], cfg["kind"], cfg["mu"])
+
+
+def _oracle_columns(args):
+    """Worker of the all-core oracle timing (a fresh interpreter: spawned, so
+    nothing of the parent's GPU runtime is inherited): regenerates the seeded
+    inputs, waits at the barrier until every worker is ready, then computes its
+    columns of W with the oracle and returns its own wall time."""
+    cfg, cols, barrier = args
+    import oracle as O
+    psi, g = _oracle_inputs(cfg)
     phi = psi[:cfg["nocc"]]
-    g = O.Grid.cubic(cfg["n"], cfg["L"], cfg["kind"], cfg["mu"])
+    O.build_W(phi, psi, g, columns=[cols[0]])          # warm (plans, pages)
+    barrier.wait()
+    t0 = time.perf_counter()
+    O.build_W(phi, psi, g, columns=cols)
+    return time.perf_counter() - t0
+
+
+def host_cores():
+    """Cores this process may run on, capped at the 16 a one-GPU machine grants."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(cfg, seconds=10.0, all_cores=True):
+    """Time the FP64 oracle's pair solves on a bounded sample of the workload,
+    in the two modes of the paper's setting and a parallel host:
+      single core  whole columns j of W (each column = N_occ pair solves), as
+                   many as fit in about `seconds` of one thread's work;
+      all cores    the oracle's columns spread over one process per host core
+                   (multiprocessing over j), each process taking as many
+                   columns as fit in about `seconds`; rate = all pairs / the
+                   slowest process's time.
+    Returns the all-core figure as the baseline (cores = processes used) with
+    the single-core one beside it."""
+    import multiprocessing as mp
+
+    import oracle as O
+    psi, g = _oracle_inputs(cfg)
+    phi = psi[:cfg["nocc"]]
     t0 = time.perf_counter()
     O.build_W(phi, psi, g, columns=[0])
-    t1 = time.perf_counter()
-    per_col = max(t1 - t0, 1e-6)
+    per_col = max(time.perf_counter() - t0, 1e-6)
     ncols = int(max(1, min(cfg["nband"] - 1, seconds / per_col)))
     t0 = time.perf_counter()
     O.build_W(phi, psi, g, columns=list(range(1, 1 + ncols)))
     dt = time.perf_counter() - t0
     pairs = ncols * cfg["nocc"]
-    return {"value": pairs / dt, "unit": "pair solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle build_W columns j=1..{ncols} ({pairs} pair solves, FP64 NumPy "
-                      f"pocketfft, single thread), {dt:.1f} s"}
+    single = {"value": pairs / dt, "unit": "pair solves/s", "cores": 1, "kind": "oracle",
+              "sample": f"oracle build_W columns j=1..{ncols} ({pairs} pair solves, FP64 "
+                        f"NumPy pocketfft, one thread), {dt:.1f} s"}
+    cores = host_cores()
+    if not all_cores or cores < 2:
+        return dict(single, host_cores=cores)
+    del psi, phi
+    per_proc = int(max(1, seconds / per_col))
+    ctx = mp.get_context("spawn")
+    with ctx.Manager() as mgr:
+        barrier = mgr.Barrier(cores)
+        jobs = [(cfg, [(k * per_proc + q) % cfg["nband"] for q in range(per_proc)], barrier)
+                for k in range(cores)]
+        with ctx.Pool(cores) as pool:
+            times = pool.map(_oracle_columns, jobs, chunksize=1)
+    pairs_all = cores * per_proc * cfg["nocc"]
+    t_all = max(times)
+    return {"value": pairs_all / t_all, "unit": "pair solves/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle build_W, {cores} processes x {per_proc} columns of W "
+                      f"({pairs_all} pair solves, FP64 NumPy pocketfft, one thread each), "
+                      f"slowest process {t_all:.1f} s",
+            "host_cores": cores, "single_core": single}
 
 
 def main():
@@ -174,7 +232,22 @@ def main():
                     info=torch.zeros(1, dtype=torch.int32, device=dev))
 
     bufs = make_bufs(cdt)
-    X_in = psi_in.reshape(nband, ng)[:nx]
+    # Orbitals V_ACE is applied to: the screened 72^3 workload applies it to
+    # X_t = generator(seed 100 + t), t < 20 (new orbitals each call, as in an
+    # eigensolver's inner iterations); the others to the first n_x orbitals
+    # of psi (V_ACE psi = W on span(psi) then checks the compression).
+    X_seeds = cfg.get("x_seeds")
+    X_host = {}
+    if X_seeds:
+        import concurrent.futures as cf
+        log(f"bench: generating {len(X_seeds)} apply inputs X_t")
+        with cf.ThreadPoolExecutor(4) as ex:
+            for sd, x in zip(X_seeds, ex.map(
+                    lambda sd: synth.smooth_orbitals(n, L, nx, seed=sd), X_seeds)):
+                X_host[sd] = torch.from_numpy(x).reshape(nx, ng).to(dev, torch.complex128)
+        Xs = [X_host[sd].to(cdt) for sd in X_seeds]
+    else:
+        Xs = None
 
     stage_ev = []
 
@@ -191,8 +264,12 @@ def main():
         ctx.compress(b["Q"], b["W"], grid, p, info=b["info"], out=b["xi"])
         if timed:
             evs[3].record()
-        for _ in range(applies):
-            ctx.apply(b["xi"], b["Q"][:nx], grid, p, out=b["Y"])
+        if b.get("X") is not None:
+            for X in b["X"]:
+                ctx.apply(b["xi"], X, grid, p, out=b["Y"])
+        else:
+            for _ in range(applies):
+                ctx.apply(b["xi"], b["Q"][:nx], grid, p, out=b["Y"])
         if timed:
             evs[4].record()
         ctx.exchange_energy(b["Q"][:nocc], grid, p, xi=b["xi"], out=b["e"])
@@ -200,6 +277,7 @@ def main():
             evs[5].record()
             stage_ev.append(evs)
 
+    bufs["X"] = Xs
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         step(prec, bufs, psi_in)
@@ -287,6 +365,7 @@ def main():
         log("bench: FP64 comparison run")
         dt64 = dtypes[ref_prec]
         b64 = make_bufs(dt64)
+        b64["X"] = [X_host[sd] for sd in X_seeds] if X_seeds else None
         psi64 = torch.from_numpy(psi_np).to(dev, dt64)
         step(ref_prec, b64, psi64)
         torch.cuda.synchronize()
@@ -315,11 +394,16 @@ def main():
         extra["errors_vs_fp64"] = {
             "W": relerr(bufs["W"], b64["W"]),
             "xi": relerr(bufs["xi"], b64["xi"]),
-            "V_ACE_psi": relerr(bufs["Y"], b64["Y"]),
+            ("V_ACE_X%d" % (len(X_seeds) - 1) if X_seeds else "V_ACE_psi"):
+                relerr(bufs["Y"], b64["Y"]),
             "E_X": abs(float(bufs["e"]) - float(b64["e"])) / abs(float(b64["e"])),
             "E_X_fp64": float(b64["e"]),
         }
         del b64, psi64
+
+    if cfg.get("golden"):
+        log("bench: errors against the oracle's stored full-size values")
+        extra["errors_vs_oracle"] = golden_errors(ctx, cfg, grid, prec, bufs, Xs, nocc)
 
     if args.copy_probe:
         src = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device=dev)
@@ -350,9 +434,64 @@ def main():
     }
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"] = with_ratios(cpu_baseline(cfg), value)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def with_ratios(cpu, gpu_value):
+    """GPU rate over the oracle's rate for each oracle mode timed."""
+    r = {"all_cores" if cpu["cores"] > 1 else "single_core": gpu_value / cpu["value"]}
+    if "single_core" in cpu:
+        r["single_core"] = gpu_value / cpu["single_core"]["value"]
+    cpu["ratio_gpu_over_oracle"] = r
+    return cpu
+
+
+def golden_errors(ctx, cfg, grid, prec, bufs, Xs, nocc):
+    """Relative errors of the run's outputs against values the FP64 oracle
+    computed for this workload (tests/golden, written by make_golden.py):
+    E_X and eig(-M) for g0 = 0 and g0 = pi/mu^2, and sampled entries of
+    V_ACE X_0 and V_ACE X_19."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_1601_07159_amd import ace
+    with open(os.path.join(ROOT, cfg["golden"])) as f:
+        gold = json.load(f)
+    out = {}
+
+    def rel(a, b):
+        a, b = np.asarray(a), np.asarray(b)
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    def samples(Y, d):
+        Yc = Y.reshape(Y.shape[0], -1)
+        idx_b = torch.tensor(d["band"], device=Y.device)
+        idx_r = torch.tensor(d["point"], device=Y.device)
+        v = Yc[idx_b, idx_r].cpu().numpy().astype(np.complex128)
+        return rel(v, np.asarray(d["re"]) + 1j * np.asarray(d["im"]))
+
+    Q = bufs["Q"]
+    for tag, g0 in (("g0_0", 0.0), ("g0_pi_over_mu2", math.pi / cfg["mu"] ** 2)):
+        gr = ace.Grid.cubic(grid.n, grid.L[0], grid.kind, grid.mu, g0)
+        W = ctx.build_W(Q[:nocc], Q, gr, prec)
+        xi, Lm = ctx.compress(Q, W, gr, prec, want_L=True)
+        e = float(ctx.exchange_energy(Q[:nocc], gr, prec, xi=xi).item())
+        eig = torch.linalg.eigvalsh((Lm @ Lm.conj().T).cpu()).numpy()
+        ref_e = gold[f"E_X_trace_{tag}"]
+        out[f"E_X_{tag}"] = abs(e - ref_e) / abs(ref_e)
+        out[f"eig_minus_M_{tag}"] = rel(eig, gold[f"eig_minus_M_{tag}"])
+        out[f"E_X_{tag}_value"] = e
+        if tag == "g0_0" and Xs:
+            out["V_ACE_X0_samples"] = samples(ctx.apply(xi, Xs[0], gr, prec), gold["apply_X0"])
+            out["V_ACE_X19_samples"] = samples(ctx.apply(xi, Xs[-1], gr, prec),
+                                               gold["apply_X19"])
+        del W, xi
+    torch.cuda.synchronize()
+    return out
 
 
 def _timed_loop(fn, steps, warmup):
@@ -431,8 +570,9 @@ def run_batched(args, cfg):
                        pairs / (ms * 1e-3), "pair solves/s", ms, "f32", config, roofline, extra)
     if not args.no_cpu:
         sp = specs[0]
-        out["cpu_baseline"] = cpu_baseline(dict(n=sp["n"], L=sp["L"], nocc=sp["nocc"],
-                                                nband=sp["nband"], kind="coulomb", mu=0.0))
+        out["cpu_baseline"] = with_ratios(
+            cpu_baseline(dict(n=sp["n"], L=sp["L"], nocc=sp["nocc"], nband=sp["nband"],
+                              kind="coulomb", mu=0.0)), out["value"])
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -495,7 +635,7 @@ def run_autograd(args, cfg):
     out = _base_record(args, cfg, "pair Poisson solves/s (E_X forward + backward)",
                        solves / (ms * 1e-3), "pair solves/s", ms, "f32", config, roofline, extra)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(dict(cfg, nband=nocc))
+        out["cpu_baseline"] = with_ratios(cpu_baseline(dict(cfg, nband=nocc)), out["value"])
     print(json.dumps(out), flush=True)
 
 

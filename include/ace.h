@@ -38,6 +38,14 @@
  *         ACE_E_ARG or ACE_E_UNSUPPORTED with nothing written.  HIP runtime
  *         failures return ACE_E_HIP; ace_last_error() gives the text.
  *         Calls on one context must not overlap from several host threads.
+ * Graph capture.  The compute entry points (build, compress, apply, energy,
+ *         gradient, orthonormalise, batched build) may be called while the
+ *         context stream is being captured into a HIP graph once the workspace
+ *         is large enough for them (ace_reserve with at least their sizes, or
+ *         an earlier uncaptured call of the same sizes).  A call that would
+ *         have to grow the workspace, or synchronise (info_dev == NULL), on a
+ *         capturing stream returns ACE_E_CAPTURE before it enqueues anything
+ *         and leaves the capture and the workspace intact.
  */
 #ifndef ACE_H
 #define ACE_H
@@ -54,14 +62,22 @@ typedef enum {
   ACE_E_NOT_PD = 2,       /* -M (or the Gram matrix) is not positive definite */
   ACE_E_NOMEM = 3,        /* device workspace allocation failed */
   ACE_E_HIP = 4,          /* a HIP runtime call failed */
-  ACE_E_UNSUPPORTED = 5   /* grid shape or precision not built into the library */
+  ACE_E_UNSUPPORTED = 5,  /* grid shape or precision not built into the library */
+  ACE_E_CAPTURE = 6       /* the call would allocate or synchronise while its stream
+                             is being captured (see "Graph capture" above) */
 } ace_status;
 
 typedef enum {
   ACE_FP64 = 0,   /* complex128 data; FFTs, products and factorisations in FP64 */
-  ACE_FP32 = 1,   /* complex64 data; FFTs and apply in FP32; M, Cholesky, xi in FP64 */
+  ACE_FP32 = 1,   /* complex64 data; FFTs and apply in FP32 (FP32 MFMA products); the
+                     compression in FP64: M = dV psi^H W and the Gram matrices of
+                     ace_orthonormalize as FP64 MFMA products of the FP32 data with FP64
+                     accumulation, Cholesky, L^{-H} and xi = W L^{-H} in FP64 */
   ACE_MIXED = 2,  /* complex64 data; FFTs and apply in FP32; M by BF16-split MFMA
-                     products with FP32 accumulation; Cholesky and xi in FP64 */
+                     products (hi/lo halves, three products) with FP32 accumulation
+                     inside each K chunk and FP64 across chunks; the Gram matrices of
+                     ace_orthonormalize by FP32 MFMA products (same accumulation);
+                     Cholesky, L^{-H} and xi = W L^{-H} in FP64 */
   ACE_REAL64 = 3, /* real orbitals (the Gamma-point setting of Section 4): arrays of
                      doubles; everything in FP64 */
   ACE_REAL32 = 4  /* real orbitals, arrays of floats; arithmetic as ACE_MIXED */
@@ -84,10 +100,19 @@ typedef struct {
 
 /* Create a context bound to a HIP stream (hipStream_t passed as void*; NULL
  * means the default stream).  The context allocates device workspace lazily on
- * the device current at creation. */
-ace_status ace_create(ace_ctx* out, void* hip_stream);
+ * the device current at creation.
+ * tune_cache (nullable): path of a tuning cache written by ace_autotune; the
+ * settings it holds are loaded now (a file that does not exist yet is not an
+ * error), and later ace_autotune calls with cache_path == NULL append their
+ * results to it. */
+ace_status ace_create(ace_ctx* out, void* hip_stream, const char* tune_cache);
 ace_status ace_destroy(ace_ctx ctx);
-/* Rebind the stream used by later calls. */
+/* Rebind the stream used by later calls.  All calls share the context's one
+ * workspace, so when the stream changes the new stream is first made to wait
+ * for the work already enqueued on the old one (an event recorded on the old
+ * stream); the calls of one context are therefore never concurrent.  When
+ * either stream is being captured no such wait is added and the caller must
+ * order the two streams itself. */
 ace_status ace_set_stream(ace_ctx ctx, void* hip_stream);
 
 /* Grow the context workspace now so that later calls with at most these sizes
@@ -126,7 +151,8 @@ ace_status ace_build_W(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  *   non-positive pivot (LAPACK potrf convention); xi is then unspecified.
  *   When info_dev is NULL the call synchronises the stream and returns
  *   ACE_E_NOT_PD on failure.
- * xi must not overlap psi or W.
+ * xi may be W itself (same pointer and ld: xi then overwrites W, through a
+ * workspace copy of n_band orbitals); otherwise xi must not overlap psi or W.
  */
 ace_status ace_compress(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                         const void* psi, long ld_psi, const void* W, long ld_W,
@@ -170,8 +196,11 @@ ace_status ace_exchange_energy_grad(ace_ctx ctx, const ace_grid* grid, ace_prec 
 /*
  * Orthonormalise n vectors: Q = X R^{-1} with <Q_a, Q_b> = delta_ab and R upper
  * triangular with positive real diagonal (the constraint of Eq. HF).  Computed
- * as two rounds of Cholesky QR in FP64 (Gram matrix, Cholesky, triangular
- * solve).  Q must not overlap X.  info_dev as in ace_compress.
+ * as two rounds of Cholesky QR (Gram matrix, Cholesky, triangular solve); the
+ * Gram matrices as FP64 MFMA products for ACE_FP64, ACE_FP32 and ACE_REAL64,
+ * FP32 MFMA products (FP32 accumulation inside each K chunk, FP64 across
+ * chunks) for ACE_MIXED and ACE_REAL32; the Cholesky and the inverse in FP64.
+ * Q must not overlap X.  info_dev as in ace_compress.
  */
 ace_status ace_orthonormalize(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                               const void* X, int n, long ld_x, void* Q, long ld_q,
@@ -210,8 +239,8 @@ ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_i
  * line shapes of the FFT passes (ACE_TUNE_FFT_SHAPE values 1, 4 and 8), and
  * keeps the fastest in the context; later builds of that grid size and
  * element size use it where the explicit knobs are not set.  cache_path
- * (nullable): the result is appended as a text line "n element_bytes budget
- * jblock shape".  Outputs (nullable): the choice (shape 0 = the defaults) and
+ * (nullable; NULL means the context's tune_cache, if any): the result is
+ * appended as a text line "n element_bytes budget jblock shape".  Outputs (nullable): the choice (shape 0 = the defaults) and
  * its time per build in ms.  Complex precisions only (ACE_E_UNSUPPORTED for the
  * real ones).
  */

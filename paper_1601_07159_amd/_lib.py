@@ -7,7 +7,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libace.so")
 
-ACE_OK, ACE_E_ARG, ACE_E_NOT_PD, ACE_E_NOMEM, ACE_E_HIP, ACE_E_UNSUPPORTED = range(6)
+(ACE_OK, ACE_E_ARG, ACE_E_NOT_PD, ACE_E_NOMEM, ACE_E_HIP, ACE_E_UNSUPPORTED,
+ ACE_E_CAPTURE) = range(7)
 ACE_FP64, ACE_FP32, ACE_MIXED, ACE_REAL64, ACE_REAL32 = 0, 1, 2, 3, 4
 ACE_COULOMB, ACE_ERFC = 0, 1
 
@@ -43,7 +44,7 @@ _d = ctypes.c_double
 _gp = ctypes.POINTER(AceGrid)
 
 _PROTOS = {
-    "ace_create": (_i, [ctypes.POINTER(_vp), _vp]),
+    "ace_create": (_i, [ctypes.POINTER(_vp), _vp, ctypes.c_char_p]),
     "ace_destroy": (_i, [_vp]),
     "ace_set_stream": (_i, [_vp, _vp]),
     "ace_reserve": (_i, [_vp, _gp, _i, _i, _i, _i]),

@@ -109,7 +109,7 @@ def _block(t: torch.Tensor, prec: int, ng: int, what: str):
 class Context:
     """An ace_ctx bound to one device; calls run on torch's current stream."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, tune_cache=None):
         self._lib = _lib.load()
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else
                            torch.device(device).index or 0)
@@ -117,7 +117,8 @@ class Context:
         h = ctypes.c_void_p()
         with torch.cuda.device(dev):
             st = self._lib.ace_create(ctypes.byref(h), ctypes.c_void_p(
-                torch.cuda.current_stream(dev).cuda_stream))
+                torch.cuda.current_stream(dev).cuda_stream),
+                tune_cache.encode() if tune_cache else None)
         if st != 0:
             raise AceError(st, "ace_create failed")
         self._h = h

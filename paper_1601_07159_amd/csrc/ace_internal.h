@@ -46,6 +46,8 @@ struct ace_ctx_s {
   int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread per line, 4 quad, 8 octet
   int num_cus = 256;
   std::string last_error;
+  std::string tune_cache;              // default cache file of ace_autotune ("" = none)
+  hipEvent_t stream_event = nullptr;   // orders a new stream after the old one
   // profiling
   bool profiling = false;
   struct ProfEntry {
@@ -70,6 +72,12 @@ namespace ace {
 
 ace_status fail(ace_ctx c, ace_status s, const std::string& msg);
 ace_status hip_fail(ace_ctx c, hipError_t e, const char* where);
+// True when the context stream is being captured into a graph (also when the
+// legacy default stream may not be used because another stream captures).
+bool stream_capturing(ace_ctx c);
+// Reads a tuning cache ("n eb budget jblock [shape]" per line) into the
+// context; a missing file returns false.
+bool tune_cache_read(ace_ctx c, const char* path);
 
 #define ACE_TRY(x)               \
   do {                           \
@@ -108,8 +116,9 @@ struct BuildPlan {
 };
 BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t elem_bytes, int nocc, int nband,
                      bool psi_starts_with_phi);
-// Workspace the compression takes for n_band vectors.
-size_t compress_ws_bytes(int nb, long ng);
+// Workspace the compression takes for n_band vectors; alias_eb > 0 adds the
+// copy of xi (n_band x N_g elements of alias_eb bytes) that xi == W needs.
+size_t compress_ws_bytes(int nb, long ng, size_t alias_eb = 0);
 // Workspace of the orthonormalisation of n vectors (element size eb).
 size_t orth_ws_bytes(int n, long ng, size_t eb);
 // Direct exchange energy: pairs per chunk and workspace.
@@ -170,10 +179,24 @@ bool overlap(Span a, Span b);
 // Compression of one instance (api.hip): M, Cholesky, xi = W L^{-H}.
 // real: the orbital blocks hold real values viewed as N_g / 2 complex numbers
 // (g.ng halved, ld halved); the small matrices then keep only their real part.
+// Arithmetic of a reduction product C = alpha A^H B (gemm_cn): kNative in the
+// data type (FP32 MFMA for complex64, FP64 for complex128), kBf16Split the
+// BF16 hi/lo products with FP32 accumulation (complex64 only), kFp64 FP64 MFMA
+// products of complex64 data with FP64 accumulation.
+enum CnMode { kNative = 0, kBf16Split = 1, kFp64 = 2 };
+// Mode of M for a precision.
+inline CnMode compress_mode(ace_prec p) {
+  return (p == ACE_MIXED || p == ACE_REAL32) ? kBf16Split : p == ACE_FP32 ? kFp64 : kNative;
+}
+// Mode of the Gram matrices of the orthonormalisation: FP64 products for
+// ACE_FP32, the data type's own MFMA otherwise.  (Not BF16-split: a Gram
+// diagonal sums |x|^2, so the dropped lo*lo term of every product is positive
+// and biases the sum instead of averaging out.)
+inline CnMode gram_mode(ace_prec p) { return p == ACE_FP32 ? kFp64 : kNative; }
 template <typename T>
 ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
                          const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
-                         cx<double>* L_out, int* info_dev, bool mixed, bool real = false);
+                         cx<double>* L_out, int* info_dev, CnMode mode, bool real = false);
 
 // Dense stages (dense.hip).  Small matrices are complex128, column-major.
 // C[a + b*ldc] = alpha * sum_r conj(A_a[r]) B_b[r]   (real_part: imaginary part
@@ -182,7 +205,7 @@ ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ld
 // or above the diagonal are computed, the others are their conjugates.
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
-                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
+                   long K, double alpha, cx<double>* C, int ldc, CnMode mode,
                    bool real_part = false, bool herm = false);
 // Y_b[r] = sum_a A_a[r] C[a + b*ldc]      (r < K); c_upper: C is upper
 // triangular and its zero blocks are skipped

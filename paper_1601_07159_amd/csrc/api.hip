@@ -21,6 +21,20 @@ ace_status hip_fail(ace_ctx c, hipError_t e, const char* where) {
   return fail(c, ACE_E_HIP, m);
 }
 
+bool stream_capturing(ace_ctx c) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(c->stream, &cs);
+  if (e == hipErrorStreamCaptureImplicit || e == hipErrorStreamCaptureUnsupported) {
+    (void)hipGetLastError();
+    return true;  // the legacy stream while another stream captures globally
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
 ace_status ws_begin(ace_ctx c, size_t total) {
   c->ws_used = 0;
   total = align_up(total ? total : 256, 256);
@@ -29,13 +43,22 @@ ace_status ws_begin(ace_ctx c, size_t total) {
     return ACE_OK;
   }
   if (total <= c->ws_bytes) return ACE_OK;
+  // Growing synchronises and allocates, neither of which a stream capture
+  // allows: refuse before touching the capture or the current buffer.
+  if (stream_capturing(c))
+    return fail(c, ACE_E_CAPTURE,
+                "the workspace must grow, which is not possible while the stream is captured "
+                "(call ace_reserve, or the same call once, before capturing)");
   if (c->ws) {
-    // queued kernels of earlier calls may still use the old buffer
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipFree(c->ws);
+    // queued kernels of earlier calls may still use the old buffer; every call
+    // of the context is ordered on its stream (ace_set_stream chains a new
+    // stream after the old one), so waiting for that stream suffices
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize(workspace)");
+    e = hipFree(c->ws);
+    if (e != hipSuccess) return hip_fail(c, e, "hipFree(workspace)");
     c->ws = nullptr;
     c->ws_bytes = 0;
-    if (e != hipSuccess) return hip_fail(c, e, "hipFree(workspace)");
   }
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, total);
@@ -70,10 +93,11 @@ size_t orth_ws_bytes(int n, long ng, size_t eb) {
   return 2 * mat + scr + 2 * 256 + tmp + 2 * gemm_cn_scratch_bytes(n, n, ng);
 }
 
-size_t compress_ws_bytes(int nb, long ng) {
+size_t compress_ws_bytes(int nb, long ng, size_t alias_eb) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
   const size_t scr = align_up(chol_scratch_elems(nb) * sizeof(cx<double>), 256);
-  return 2 * mat + scr + 256 + gemm_cn_scratch_bytes(nb, nb, ng);
+  const size_t copy = alias_eb ? align_up((size_t)nb * ng * alias_eb, 256) : 0;
+  return 2 * mat + scr + 256 + gemm_cn_scratch_bytes(nb, nb, ng) + copy;
 }
 
 void prof_begin(ace_ctx c, const char* name, int* entry, hipEvent_t* e0) {
@@ -229,30 +253,41 @@ static ace_status finish_info(ace_ctx c, int* info_ws, int* info_dev) {
 template <typename T>
 ace_status compress_impl(ace_ctx c, const GridInfo& g, const cx<T>* psi, long ldpsi,
                          const cx<T>* W, long ldW, int nb, cx<T>* xi, long ldxi,
-                         cx<double>* L_out, int* info_dev, bool mixed, bool real) {
+                         cx<double>* L_out, int* info_dev, CnMode mode, bool real) {
   const size_t mat = align_up((size_t)nb * nb * sizeof(cx<double>), 256);
-  ACE_TRY(ws_begin(c, compress_ws_bytes(nb, g.ng)));
+  // xi == W: the expansion's column blocks read every column of W for their
+  // rows, so xi is formed in a workspace copy and copied over W at the end
+  const bool alias = (const void*)xi == (const void*)W;
+  ACE_TRY(ws_begin(c, compress_ws_bytes(nb, g.ng, alias ? sizeof(cx<T>) : 0)));
   ace_status st = ACE_OK;
   cx<double>* M = (cx<double>*)ws_take(c, mat, &st);
   cx<double>* X = (cx<double>*)ws_take(c, chol_scratch_elems(nb) * sizeof(cx<double>), &st);
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   int* info = (int*)ws_take(c, 256, &st);
-  if (!M || !X || !C || !info) return st;
-  // M = dV psi^H W, then -M made exactly Hermitian
-  // M is Hermitian (V_X is): its upper triangle of tiles defines it
-  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mixed, real, true));
+  cx<T>* tmp = alias ? (cx<T>*)ws_take(c, (size_t)nb * g.ng * sizeof(cx<T>), &st) : nullptr;
+  if (!M || !X || !C || !info || (alias && !tmp)) return st;
+  // M = dV psi^H W; M is Hermitian (V_X is): its upper triangle of tiles
+  // defines it
+  ACE_TRY(gemm_cn<T>(c, psi, ldpsi, nb, W, ldW, nb, g.ng, g.dV, M, nb, mode, real, true));
   // -M made exactly Hermitian, -M = L L^H, C = L^{-H}
   ACE_TRY(chol_inv(c, M, nb, -1.0, L_out, C, X, info, nullptr, real));
-  ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, xi, ldxi, g.ng, true, true));
+  ACE_TRY(gemm_nn<T>(c, W, ldW, nb, C, nb, nb, alias ? tmp : xi, alias ? g.ng : ldxi, g.ng, true,
+                     true));
+  if (alias) {
+    const hipError_t e = hipMemcpy2DAsync(xi, (size_t)ldxi * sizeof(cx<T>), tmp,
+                                          (size_t)g.ng * sizeof(cx<T>), (size_t)g.ng * sizeof(cx<T>),
+                                          (size_t)nb, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpy2DAsync(xi)");
+  }
   return finish_info(c, info, info_dev);
 }
 
 template ace_status compress_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, long,
                                          const cx<float>*, long, int, cx<float>*, long,
-                                         cx<double>*, int*, bool, bool);
+                                         cx<double>*, int*, CnMode, bool);
 template ace_status compress_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, long,
                                           const cx<double>*, long, int, cx<double>*, long,
-                                          cx<double>*, int*, bool, bool);
+                                          cx<double>*, int*, CnMode, bool);
 
 template <typename T>
 static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb, long ldxi,
@@ -263,7 +298,7 @@ static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb,
   ace_status st = ACE_OK;
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   if (!C) return st;
-  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, X, ldx, nx, g.ng, -g.dV, C, nb, false, real));
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, X, ldx, nx, g.ng, -g.dV, C, nb, kNative, real));
   return gemm_nn<T>(c, xi, ldxi, nb, C, nb, nx, Y, ldy, g.ng, false);
 }
 
@@ -276,13 +311,13 @@ static ace_status energy_ace_t(ace_ctx c, const GridInfo& g, const cx<T>* phi, i
   ace_status st = ACE_OK;
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   if (!C) return st;
-  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, phi, ldphi, nocc, g.ng, g.dV, C, nb, false, real));
+  ACE_TRY(gemm_cn<T>(c, xi, ldxi, nb, phi, ldphi, nocc, g.ng, g.dV, C, nb, kNative, real));
   return sumsq(c, C, (long)nb * nocc, -0.5, ex);
 }
 
 template <typename T>
 static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, long ldx, cx<T>* Q,
-                         long ldq, int* info_dev, bool real = false) {
+                         long ldq, int* info_dev, CnMode mode, bool real = false) {
   const size_t mat = align_up((size_t)n * n * sizeof(cx<double>), 256);
   const size_t tmp = align_up((size_t)n * g.ng * sizeof(cx<T>), 256);
   const size_t scr = align_up(chol_scratch_elems(n) * sizeof(cx<double>), 256);
@@ -296,11 +331,11 @@ static ace_status orth_t(ace_ctx c, const GridInfo& g, const cx<T>* X, int n, lo
   cx<T>* Y = (cx<T>*)ws_take(c, tmp, &st);
   if (!S || !Xs || !C || !info1 || !info2 || !Y) return st;
   // first pass: Y = X R1^{-1}, S = dV X^H X = R1^H R1 with R1 = L^H
-  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, false, real, true));
+  ACE_TRY(gemm_cn<T>(c, X, ldx, n, X, ldx, n, g.ng, g.dV, S, n, mode, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info1, nullptr, real));
   ACE_TRY(gemm_nn<T>(c, X, ldx, n, C, n, n, Y, g.ng, g.ng, true, true));
   // the second pass on Y restores orthogonality lost to rounding in the first
-  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, false, real, true));
+  ACE_TRY(gemm_cn<T>(c, Y, g.ng, n, Y, g.ng, n, g.ng, g.dV, S, n, mode, real, true));
   ACE_TRY(chol_inv(c, S, n, 1.0, nullptr, C, Xs, info2, info1, real));
   ACE_TRY(gemm_nn<T>(c, Y, g.ng, n, C, n, n, Q, ldq, g.ng, true, true));
   return finish_info(c, info2, info_dev);
@@ -318,6 +353,7 @@ ACE_EXPORT const char* ace_status_string(ace_status s) {
     case ACE_E_NOMEM: return "out of device memory";
     case ACE_E_HIP: return "HIP runtime error";
     case ACE_E_UNSUPPORTED: return "unsupported configuration";
+    case ACE_E_CAPTURE: return "not allowed while the stream is being captured";
   }
   return "unknown status";
 }
@@ -337,12 +373,16 @@ ACE_EXPORT int ace_supported_n(int* out, int cap) {
   return out ? k : count;
 }
 
-ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream) {
+ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream, const char* tune_cache) {
   if (!out) return ACE_E_ARG;
   *out = nullptr;
   ace_ctx c = new (std::nothrow) ace_ctx_s();
   if (!c) return ACE_E_NOMEM;
   c->stream = (hipStream_t)stream;
+  if (tune_cache) {
+    c->tune_cache = tune_cache;
+    (void)tune_cache_read(c, tune_cache);  // a cache not written yet is not an error
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return ACE_E_HIP;
@@ -369,6 +409,7 @@ ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
     hipStreamDestroy(c->capture_stream);
   }
   if (c->fork_event) hipEventDestroy(c->fork_event);
+  if (c->stream_event) hipEventDestroy(c->stream_event);
   if (c->ws) {
     hipStreamSynchronize(c->stream);
     hipFree(c->ws);
@@ -384,7 +425,26 @@ ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
 
 ACE_EXPORT ace_status ace_set_stream(ace_ctx c, void* stream) {
   if (!c) return ACE_E_ARG;
-  c->stream = (hipStream_t)stream;
+  const hipStream_t next = (hipStream_t)stream;
+  if (next == c->stream) return ACE_OK;
+  // The calls share one workspace: the new stream waits for what the old one
+  // has queued (skipped when either is capturing; the caller orders them then).
+  const hipStream_t prev = c->stream;
+  const bool prev_cap = stream_capturing(c);
+  c->stream = next;
+  const bool next_cap = stream_capturing(c);
+  if (prev_cap || next_cap) return ACE_OK;
+  if (!c->stream_event) {
+    const hipError_t e = hipEventCreateWithFlags(&c->stream_event, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      c->stream_event = nullptr;
+      c->stream = prev;
+      return hip_fail(c, e, "hipEventCreateWithFlags");
+    }
+  }
+  hipError_t e = hipEventRecord(c->stream_event, prev);
+  if (e == hipSuccess) e = hipStreamWaitEvent(next, c->stream_event, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "ordering the new stream");
   return ACE_OK;
 }
 
@@ -438,7 +498,7 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
       need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nband, symm).bytes);
       need = std::max(need, plan_build_real(c, g, 2 * eb, max_nocc, max_nocc, symm).bytes);
     }
-    need = std::max(need, compress_ws_bytes(max_nband, gh.ng));
+    need = std::max(need, compress_ws_bytes(max_nband, gh.ng, 2 * eb));
     need = std::max(need, orth_ws_bytes(nmax, gh.ng, 2 * eb));
     need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), gh.ng));
     need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, max_nocc, gh.ng));
@@ -447,7 +507,7 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   size_t need = std::max(plan_build(c, g, eb, max_nocc, max_nband, true).bytes,
                          plan_build(c, g, eb, max_nocc, max_nband, false).bytes);
   need = std::max(need, plan_build(c, g, eb, max_nocc, max_nocc, true).bytes);
-  need = std::max(need, compress_ws_bytes(max_nband, g.ng));
+  need = std::max(need, compress_ws_bytes(max_nband, g.ng, eb));
   need = std::max(need, orth_ws_bytes(nmax, g.ng, eb));
   need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), g.ng));
   need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, max_nocc, g.ng));
@@ -496,9 +556,12 @@ ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec pre
   if (n_band > 4096) return fail(c, ACE_E_UNSUPPORTED, "n_band above 4096");
   const size_t eb = elem_bytes(prec);
   const Span sx = span_of(xi, n_band, ld_xi, g.ng, eb);
+  const bool alias = xi == W && ld_xi == ld_W;
   if (overlap(sx, span_of(psi, n_band, ld_psi, g.ng, eb)) ||
-      overlap(sx, span_of(W, n_band, ld_W, g.ng, eb)))
-    return fail(c, ACE_E_ARG, "xi overlaps an input");
+      (!alias && overlap(sx, span_of(W, n_band, ld_W, g.ng, eb))))
+    return fail(c, ACE_E_ARG, "xi overlaps an input (it may only be W itself, same ld)");
+  if (!info_dev && stream_capturing(c))
+    return fail(c, ACE_E_CAPTURE, "info_dev == NULL synchronises, which a capture does not allow");
   if (is_real(prec)) {
     ACE_TRY(check_real_view(c, psi, ld_psi, eb, "psi"));
     ACE_TRY(check_real_view(c, W, ld_W, eb, "W"));
@@ -507,17 +570,18 @@ ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec pre
     if (prec == ACE_REAL64)
       return compress_impl<double>(c, gh, (const cx<double>*)psi, ld_psi / 2,
                                    (const cx<double>*)W, ld_W / 2, n_band, (cx<double>*)xi,
-                                   ld_xi / 2, (cx<double>*)L_out, info_dev, false, true);
+                                   ld_xi / 2, (cx<double>*)L_out, info_dev, kNative, true);
     return compress_impl<float>(c, gh, (const cx<float>*)psi, ld_psi / 2, (const cx<float>*)W,
                                 ld_W / 2, n_band, (cx<float>*)xi, ld_xi / 2, (cx<double>*)L_out,
-                                info_dev, true, true);
+                                info_dev, compress_mode(prec), true);
   }
   if (prec == ACE_FP64)
     return compress_impl<double>(c, g, (const cx<double>*)psi, ld_psi, (const cx<double>*)W, ld_W,
-                              n_band, (cx<double>*)xi, ld_xi, (cx<double>*)L_out, info_dev, false);
+                                 n_band, (cx<double>*)xi, ld_xi, (cx<double>*)L_out, info_dev,
+                                 kNative);
   return compress_impl<float>(c, g, (const cx<float>*)psi, ld_psi, (const cx<float>*)W, ld_W, n_band,
-                           (cx<float>*)xi, ld_xi, (cx<double>*)L_out, info_dev,
-                           prec == ACE_MIXED);
+                              (cx<float>*)xi, ld_xi, (cx<double>*)L_out, info_dev,
+                              compress_mode(prec));
 }
 
 ACE_EXPORT ace_status ace_apply(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* xi,
@@ -626,19 +690,23 @@ ACE_EXPORT ace_status ace_orthonormalize(ace_ctx c, const ace_grid* grid, ace_pr
   const size_t eb = elem_bytes(prec);
   if (overlap(span_of(Q, n, ld_q, g.ng, eb), span_of(X, n, ld_x, g.ng, eb)))
     return fail(c, ACE_E_ARG, "Q overlaps X");
+  if (!info_dev && stream_capturing(c))
+    return fail(c, ACE_E_CAPTURE, "info_dev == NULL synchronises, which a capture does not allow");
+  const CnMode mode = gram_mode(prec);
   if (is_real(prec)) {
     ACE_TRY(check_real_view(c, X, ld_x, eb, "X"));
     ACE_TRY(check_real_view(c, Q, ld_q, eb, "Q"));
     const GridInfo gh = half_view(g);
     if (prec == ACE_REAL64)
       return orth_t<double>(c, gh, (const cx<double>*)X, n, ld_x / 2, (cx<double>*)Q, ld_q / 2,
-                            info_dev, true);
+                            info_dev, mode, true);
     return orth_t<float>(c, gh, (const cx<float>*)X, n, ld_x / 2, (cx<float>*)Q, ld_q / 2,
-                         info_dev, true);
+                         info_dev, mode, true);
   }
   if (prec == ACE_FP64)
-    return orth_t<double>(c, g, (const cx<double>*)X, n, ld_x, (cx<double>*)Q, ld_q, info_dev);
-  return orth_t<float>(c, g, (const cx<float>*)X, n, ld_x, (cx<float>*)Q, ld_q, info_dev);
+    return orth_t<double>(c, g, (const cx<double>*)X, n, ld_x, (cx<double>*)Q, ld_q, info_dev,
+                          mode);
+  return orth_t<float>(c, g, (const cx<float>*)X, n, ld_x, (cx<float>*)Q, ld_q, info_dev, mode);
 }
 
 ACE_EXPORT ace_status ace_profile_enable(ace_ctx c, int on) {

@@ -44,12 +44,12 @@ ace_status ensure_branches(ace_ctx c, int nb) {
 }
 
 template <typename T>
-ace_status enqueue_instance(ace_ctx c, const ace_instance& in, const GridInfo& g, bool mixed) {
+ace_status enqueue_instance(ace_ctx c, const ace_instance& in, const GridInfo& g, CnMode mode) {
   ACE_TRY(build_W_impl<T>(c, g, (const cx<T>*)in.phi, in.n_occ, in.ld_phi, (const cx<T>*)in.psi,
                           in.n_band, in.ld_psi, (cx<T>*)in.W, in.ld_W, in.scale));
   if (in.xi)
     ACE_TRY(compress_impl<T>(c, g, (const cx<T>*)in.psi, in.ld_psi, (const cx<T>*)in.W, in.ld_W,
-                             in.n_band, (cx<T>*)in.xi, in.ld_xi, nullptr, in.info_dev, mixed));
+                             in.n_band, (cx<T>*)in.xi, in.ld_xi, nullptr, in.info_dev, mode));
   return ACE_OK;
 }
 
@@ -167,8 +167,8 @@ ACE_EXPORT ace_status ace_build_batched(ace_ctx c, ace_prec prec, int n_inst,
     c->sub_bytes = bbytes[b];
     for (int k = 0; k < n_inst && st == ACE_OK; ++k) {
       if (plan[k].branch != b) continue;
-      st = prec == ACE_FP64 ? enqueue_instance<double>(c, inst[k], plan[k].g, false)
-                            : enqueue_instance<float>(c, inst[k], plan[k].g, prec == ACE_MIXED);
+      st = prec == ACE_FP64 ? enqueue_instance<double>(c, inst[k], plan[k].g, kNative)
+                            : enqueue_instance<float>(c, inst[k], plan[k].g, compress_mode(prec));
     }
     if (st == ACE_OK) {
       e = hipEventRecord(c->branch_events[b], c->stream);

@@ -381,6 +381,45 @@ __device__ __forceinline__ cx<T> quad_swap(cx<T> a) {
   return {quad_swap<CTRL>(a.x), quad_swap<CTRL>(a.y)};
 }
 
+// Value held by lane (l ^ D) of the wave: D = 1, 2 by DPP quad permutations;
+// D = 16, 32 by the gfx950 permlane swaps, whose lane layout (measured with a
+// probe): permlane16_swap(x, x) returns, in every pair of 16-lane rows, the
+// even row's value in [0] and the odd row's in [1]; permlane32_swap(x, x)
+// returns the lower 32 lanes' value in [0] and the upper 32 lanes' in [1].
+template <int D>
+__device__ __forceinline__ unsigned lane_xor_u32(unsigned u) {
+  static_assert(D == 1 || D == 2 || D == 16 || D == 32, "lane distance");
+  if constexpr (D == 1) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, kQuadXor1, 0xF, 0xF, false);
+  } else if constexpr (D == 2) {
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, kQuadXor2, 0xF, 0xF, false);
+  } else {
+    const bool upper = (__lane_id() & D) != 0;
+    if constexpr (D == 16) {
+      const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+      return upper ? r[0] : r[1];
+    } else {
+      const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+      return upper ? r[0] : r[1];
+    }
+  }
+}
+template <int D>
+__device__ __forceinline__ float lane_xor(float x) {
+  return __builtin_bit_cast(float, lane_xor_u32<D>(__builtin_bit_cast(unsigned, x)));
+}
+template <int D>
+__device__ __forceinline__ double lane_xor(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = lane_xor_u32<D>((unsigned)(u & 0xffffffffULL));
+  const unsigned hi = lane_xor_u32<D>((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | (unsigned long long)lo);
+}
+template <int D, typename T>
+__device__ __forceinline__ cx<T> lane_xor(cx<T> a) {
+  return {lane_xor<D>(a.x), lane_xor<D>(a.y)};
+}
+
 template <int N, int S, typename T>
 __device__ __forceinline__ void quad_twiddle(cx<T>* v, int h) {
   constexpr int M = N / 4;
@@ -394,7 +433,11 @@ __device__ __forceinline__ void quad_twiddle(cx<T>* v, int h) {
   }
 }
 
-template <int N, int S, typename T>
+// D1: lane distance between the parts h and h ^ 1 of a line (1: the 4 lanes
+// of a quad; 16: lanes l, l + 16, l + 32, l + 48, so that 16 consecutive
+// lanes hold the same part of 16 lines, which keeps their global accesses
+// contiguous); parts h and h ^ 2 are 2 D1 apart.
+template <int N, int S, typename T, int D1 = 1>
 __device__ __forceinline__ void fft_quad_d2b(cx<T>* v, int h) {
   constexpr int M = N / 4;
   static_assert(N % 4 == 0, "quad lines need N divisible by 4");
@@ -403,12 +446,12 @@ __device__ __forceinline__ void fft_quad_d2b(cx<T>* v, int h) {
   const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
 #pragma unroll
   for (int k = 0; k < M; ++k) {  // lanes h, h^2: (u, w) -> (u + w, u - w)
-    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    const cx<T> p = lane_xor<2 * D1>(v[k]);
     v[k] = hi ? csub(p, v[k]) : cadd(v[k], p);
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {  // lanes h, h^1: (u, w) -> (u + t w, u - t w), t = (S i)^(h >> 1)
-    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    const cx<T> p = lane_xor<D1>(v[k]);
     const cx<T> q = odd ? v[k] : p;
     const cx<T> r = odd ? p : v[k];
     const cx<T> tq = hi ? mul_si<S>(q) : q;
@@ -416,19 +459,19 @@ __device__ __forceinline__ void fft_quad_d2b(cx<T>* v, int h) {
   }
 }
 
-template <int N, int S, typename T>
+template <int N, int S, typename T, int D1 = 1>
 __device__ __forceinline__ void fft_quad_b2d(cx<T>* v, int h) {
   constexpr int M = N / 4;
   static_assert(N % 4 == 0, "quad lines need N divisible by 4");
   const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
 #pragma unroll
   for (int k = 0; k < M; ++k) {  // lanes L, L^1 hold X[c], X[c + 2]: sum and difference
-    const cx<T> p = quad_swap<kQuadXor1>(v[k]);
+    const cx<T> p = lane_xor<D1>(v[k]);
     v[k] = odd ? csub(p, v[k]) : cadd(v[k], p);
   }
 #pragma unroll
   for (int k = 0; k < M; ++k) {  // lanes L, L^2: the odd pair carries the factor S i
-    const cx<T> p = quad_swap<kQuadXor2>(v[k]);
+    const cx<T> p = lane_xor<2 * D1>(v[k]);
     const cx<T> q = hi ? v[k] : p;
     const cx<T> r = hi ? p : v[k];
     const cx<T> wq = odd ? mul_si<S>(q) : q;

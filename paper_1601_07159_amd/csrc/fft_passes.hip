@@ -509,7 +509,28 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
 #pragma unroll
   for (int k = 0; k < N; ++k) acc[k * 64 + t] = cx<T>{T(0), T(0)};
   const int j = j0 + b;
-  for (int a = 0; a < A; ++a) {
+  // Bands of a triangle block take their orbitals in round-robin tournament
+  // order (the circle method over the block's A bands, a bye when A is odd):
+  // at step s band b meets partner p(s, b), and p(s, p(s, b)) = b, so the two
+  // waves that need the spectrum of the pair {b, p} (one as u, one as conj u)
+  // read it at the same step, and the second read finds it in cache.
+  const bool tri = mode == 1 || (mode == 3 && b < A);
+  const int rounds = A - 1 + (A & 1);  // players A (+1 bye when odd), fixed player m
+  for (int s = 0; s < A; ++s) {
+    int a = s;
+    if (tri) {
+      const int m = rounds;
+      if (s >= rounds) {
+        a = b;  // even A: the band's own pair last
+      } else if (b == m) {
+        a = s;
+      } else {
+        int q = (2 * s - b) % m;
+        q = q < 0 ? q + m : q;
+        a = q == b ? m : q;
+        if (a == A) a = b;  // odd A: the bye is the band's own pair
+      }
+    }
     const int i = i0 + a;
     size_t pidx;
     bool conj_u;
@@ -553,6 +574,96 @@ __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ p
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) w[k * N] = acc[k * 64 + t];
+  }
+}
+
+// Index of the orbital that band b of a triangle block (A bands) meets at step
+// s: the round-robin tournament of k_pencil_accum (circle method, a bye when A
+// is odd, the band's own pair at the bye or, for even A, at the last step).
+__device__ __forceinline__ int tri_partner(int A, int b, int s) {
+  const int m = A - 1 + (A & 1);
+  if (s >= m) return b;
+  if (b == m) return s;
+  int q = (2 * s - b) % m;
+  q = q < 0 ? q + m : q;
+  const int a = q == b ? m : q;
+  return a == A ? b : a;
+}
+
+// Accumulate pass on split lines: every (x0, x2) pencil along axis 1 is split
+// over 4 lanes 16 apart (lane p + 16 h holds part h of pencil p: it loads rows
+// h + 4 m and, after fft_quad_d2b, holds rows k + M kp(h)), 16 consecutive
+// pencils per one-wave workgroup, so every load and store of 16 lanes is one
+// contiguous row segment; one band per workgroup row of the grid.  The band's
+// accumulator stays in registers (no LDS), so occupancy is set by registers
+// alone.  Modes, pair indices and the tournament order of the triangle bands
+// as in k_pencil_accum.
+template <int N, typename T>
+__global__ __launch_bounds__(64) void k_pencil_accum_q(const cx<T>* __restrict__ phi, long ldphi,
+                                                       const cx<T>* __restrict__ buf,
+                                                       cx<T>* __restrict__ W, long ldW, int i0,
+                                                       int A, int j0, int nbc, int accumulate,
+                                                       int mode) {
+  constexpr int NN = N * N;
+  constexpr int M = N / 4;
+  constexpr int TILES = NN / 16;  // N is a multiple of 4
+  static_assert(N % 4 == 0, "quad lines need N divisible by 4");
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)TILES * nbc) return;
+  const int tile = (int)(lid / nbc);
+  const int b = (int)(lid - (long)tile * nbc);
+  const int h = (int)threadIdx.x >> 4;
+  const int q = tile * 16 + ((int)threadIdx.x & 15);
+  const int x0 = q / N, x2 = q - x0 * N;
+  const size_t off = (size_t)x0 * NN + x2;
+  cx<T> acc[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) acc[k] = cx<T>{T(0), T(0)};
+  const int j = j0 + b;
+  const bool tri = mode == 1 || (mode == 3 && b < A);
+  for (int s = 0; s < A; ++s) {
+    const int a = tri ? tri_partner(A, b, s) : s;
+    const int i = i0 + a;
+    size_t pidx;
+    bool conj_u;
+    if (mode == 0) {
+      pidx = (size_t)a + (size_t)A * b;
+      conj_u = false;
+    } else if (tri) {
+      pidx = a <= b ? (size_t)b * (b + 1) / 2 + a : (size_t)a * (a + 1) / 2 + b;
+      conj_u = a > b;
+    } else if (mode == 3) {
+      pidx = (size_t)A * (A + 1) / 2 + (size_t)a + (size_t)A * (b - A);
+      conj_u = false;
+    } else {
+      pidx = (size_t)b + (size_t)nbc * a;
+      conj_u = true;
+    }
+    const cx<T>* src = buf + pidx * N * NN + off;
+    const cx<T>* fp = phi + (size_t)i * ldphi + off;
+    cx<T> v[M], f[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = src[(size_t)(h + 4 * m) * N];
+#pragma unroll
+    for (int k = 0; k < M; ++k) f[k] = fp[(size_t)quad_block_index(k, M, h) * N];
+    fft_quad_d2b<N, +1, T, 16>(v, h);
+    const T sg = conj_u ? T(-1) : T(1);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const cx<T> u = {v[k].x, sg * v[k].y};
+      acc[k] = cadd(acc[k], cmul(f[k], u));
+    }
+  }
+  cx<T>* w = W + (size_t)j * ldW + off;
+  if (accumulate) {
+    cx<T> old[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) old[k] = w[(size_t)quad_block_index(k, M, h) * N];
+#pragma unroll
+    for (int k = 0; k < M; ++k) w[(size_t)quad_block_index(k, M, h) * N] = cadd(old[k], acc[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k) w[(size_t)quad_block_index(k, M, h) * N] = acc[k];
   }
 }
 
@@ -1092,6 +1203,21 @@ ace_status plane(ace_ctx c, bool quad, cx<T>* buf, const T* Kt, int np) {
                 dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, buf, Kt, np);
 }
 
+// Accumulate pass: the quad form by default; one thread per pencil (LDS
+// accumulator) when the line-shape knob asks for one thread per line.
+template <int N, typename T>
+ace_status accum(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* buf, cx<T>* W, long ldW,
+                 int i0, int A, int j0, int nbc, int accumulate, int mode) {
+  if (line_shape(c, N, (int)sizeof(cx<T>)) == 1) {
+    constexpr int TILES = (N * N + 63) / 64;
+    return launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nbc)),
+                  dim3(64), 0, phi, ldphi, buf, W, ldW, i0, A, j0, nbc, accumulate, mode);
+  }
+  constexpr int TQ = N * N / 16;
+  return launch(c, "pencil_accum", k_pencil_accum_q<N, T>, dim3(xcd_pad((long)TQ * nbc)),
+                dim3(64), 0, phi, ldphi, buf, W, ldW, i0, A, j0, nbc, accumulate, mode);
+}
+
 template <int N, typename T>
 ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                      const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale,
@@ -1112,15 +1238,13 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
   const bool quad = use_quad<N, T>(c, false), quad_p = use_quad<N, T>(c, true);
   int jstart = 0;
-  const dim3 pgrid_occ(xcd_pad((long)TILES * nocc));
   if (pl.merged) {
     const long all = (long)nocc * (nocc + 1) / 2 + (long)nocc * (nband - nocc);
     if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 3, 0, nocc, nocc, 0L,
                              (int)all)) != ACE_OK)
       return st;
     if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)all)) != ACE_OK) return st;
-    return launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nband)),
-                  dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, 0, nocc, 0, nband, 0, 3);
+    return accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nband, 0, 3);
   }
   if (sym && pl.symblk == 0) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
@@ -1130,8 +1254,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
         ACE_OK)
       return st;
     if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)tri)) != ACE_OK) return st;
-    if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, pgrid_occ, dim3(64), 0, phi, ldphi,
-                     (const cx<T>*)buf, W, ldW, 0, nocc, 0, nocc, 0, 1)) != ACE_OK)
+    if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nocc, 0, 1)) != ACE_OK)
       return st;
     jstart = nocc;
   } else if (sym) {
@@ -1149,9 +1272,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
               ACE_OK)
             return st;
           if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
-          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
-                           dim3(xcd_pad((long)TILES * ni)), dim3(64), 0, phi, ldphi,
-                           (const cx<T>*)buf, W, ldW, i0, ni, i0, ni, (int)started[I], 1)) !=
+          if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, i0, ni, (int)started[I], 1)) !=
               ACE_OK)
             return st;
           started[I] = 1;
@@ -1162,15 +1283,11 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
             return st;
           if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
           // bands of J from the orbitals of I, then bands of I from those of J
-          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
-                           dim3(xcd_pad((long)TILES * nj)), dim3(64), 0, phi, ldphi,
-                           (const cx<T>*)buf, W, ldW, i0, ni, j0, nj, (int)started[J], 0)) !=
+          if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, j0, nj, (int)started[J], 0)) !=
               ACE_OK)
             return st;
           started[J] = 1;
-          if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>,
-                           dim3(xcd_pad((long)TILES * ni)), dim3(64), 0, phi, ldphi,
-                           (const cx<T>*)buf, W, ldW, j0, nj, i0, ni, (int)started[I], 2)) !=
+          if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, j0, nj, i0, ni, (int)started[I], 2)) !=
               ACE_OK)
             return st;
           started[I] = 1;
@@ -1187,9 +1304,8 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
           ACE_OK)
         return st;
       if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
-      if ((st = launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * Bc)),
-                       dim3(64), 0, phi, ldphi, (const cx<T>*)buf, W, ldW, i0, Ac, j0, Bc,
-                       i0 > 0 ? 1 : 0, 0)) != ACE_OK)
+      if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, Ac, j0, Bc, i0 > 0 ? 1 : 0, 0)) !=
+          ACE_OK)
         return st;
     }
   }

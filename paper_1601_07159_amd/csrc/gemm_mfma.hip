@@ -161,11 +161,13 @@ __device__ __forceinline__ TileRows<T> tile_rows_herm(const cx<T>* A, long lda, 
   return t;
 }
 
-template <typename T>
-__global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
+// T: the data type; TAcc: the MFMA and accumulation type (T, or double for
+// FP64 products of complex64 data).
+template <typename T, typename TAcc>
+__global__ __launch_bounds__(sizeof(TAcc) == 8 ? 512 : 1024) void k_cn_mfma(
     const cx<T>* __restrict__ A, long lda, int na, const cx<T>* __restrict__ B, long ldb, int nb,
-    long K, long kchunk, cx<T>* __restrict__ partial, int herm) {
-  typedef typename Acc4<T>::type acc_t;
+    long K, long kchunk, cx<TAcc>* __restrict__ partial, int herm) {
+  typedef typename Acc4<TAcc>::type acc_t;
   const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
   const TileRows<T> t = herm ? tile_rows_herm<T>(A, lda, na, B, ldb, nb, r16)
                              : tile_rows<T>(A, lda, na, B, ldb, nb, r16);
@@ -220,9 +222,10 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
               if (!F && (!t.ba[x] || !t.bb[y])) continue;
-              const T av = kin[j] ? a[j][x][s] : T(0);
-              const T bpp = (s & 1) ? -b[j][y][s ^ 1] : b[j][y][s ^ 1];
-              cre[x][y] = mfma4(av, b[j][y][s], cre[x][y]);
+              const TAcc av = kin[j] ? (TAcc)a[j][x][s] : TAcc(0);
+              const TAcc bv = (TAcc)b[j][y][s];
+              const TAcc bpp = (TAcc)((s & 1) ? -b[j][y][s ^ 1] : b[j][y][s ^ 1]);
+              cre[x][y] = mfma4(av, bv, cre[x][y]);
               cim[x][y] = mfma4(av, bpp, cim[x][y]);
             }
       }
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void k_cn_mfma(
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int ra = t.a0 + 16 * x + mfma_row<T>(lane, v);
+        const int ra = t.a0 + 16 * x + mfma_row<TAcc>(lane, v);
         const int rb = t.b0 + 16 * y + r16;
         if (ra < na && rb < nb)
           partial[((size_t)blockIdx.z * nb + rb) * na + ra] = {cre[x][y][v], cim[x][y][v]};
@@ -732,38 +735,49 @@ size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
 
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
-                   long K, double alpha, cx<double>* C, int ldc, bool bf16_split,
+                   long K, double alpha, cx<double>* C, int ldc, CnMode mode,
                    bool real_part, bool herm) {
+  const bool bf16_split = std::is_same<T, float>::value && mode == kBf16Split;
+  const bool f64 = sizeof(T) == 8 || mode == kFp64;
   // the BF16-split kernel addresses a tile's 32 rows through a buffer
   // resource with 32-bit byte offsets
   if (bf16_split && (lda > (1L << 31) / 256 || ldb > (1L << 31) / 256))
     return fail(c, ACE_E_UNSUPPORTED, "leading dimension too large for the BF16-split product");
-  const int max_waves = sizeof(T) == 8 ? 8 : bf16_split ? 12 : 16;
-  const int cu_waves = sizeof(T) == 8 ? 12 : bf16_split ? 12 : 16;
+  const int max_waves = f64 ? 8 : bf16_split ? 12 : 16;
+  const int cu_waves = f64 ? 12 : bf16_split ? 12 : 16;
   CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
   herm = herm && na == nb && herm_shape(na, K, max_waves, cu_waves, &s);
   const int hm = herm ? 1 : 0;
   ace_status st;
-  cx<T>* partial = (cx<T>*)ws_take(c, (size_t)s.ks * na * nb * sizeof(cx<T>), &st);
+  const size_t part_eb = f64 ? sizeof(cx<double>) : sizeof(cx<float>);
+  void* partial = ws_take(c, (size_t)s.ks * na * nb * part_eb, &st);
   if (!partial) return st;
   const dim3 grid((unsigned)s.gx, (unsigned)s.gy, (unsigned)s.ks);
   const dim3 block(64 * s.ta, s.tb);
   if constexpr (std::is_same<T, float>::value) {
     if (bf16_split) {
       if ((st = launch(c, "cn_mfma_bf16x3", k_cn_mfma_bf16x3, grid, block, 0, A, lda, na, B, ldb,
-                       nb, K, s.kchunk, partial, hm)) != ACE_OK)
+                       nb, K, s.kchunk, (cx<float>*)partial, hm)) != ACE_OK)
         return st;
-    } else if ((st = launch(c, "cn_mfma_f32", k_cn_mfma<float>, grid, block, 0, A, lda, na, B,
-                            ldb, nb, K, s.kchunk, partial, hm)) != ACE_OK) {
+    } else if (f64) {
+      if ((st = launch(c, "cn_mfma_f32in_f64", k_cn_mfma<float, double>, grid, block, 0, A, lda,
+                       na, B, ldb, nb, K, s.kchunk, (cx<double>*)partial, hm)) != ACE_OK)
+        return st;
+    } else if ((st = launch(c, "cn_mfma_f32", k_cn_mfma<float, float>, grid, block, 0, A, lda, na,
+                            B, ldb, nb, K, s.kchunk, (cx<float>*)partial, hm)) != ACE_OK) {
       return st;
     }
   } else {
-    if ((st = launch(c, "cn_mfma_f64", k_cn_mfma<double>, grid, block, 0, A, lda, na, B, ldb, nb,
-                     K, s.kchunk, partial, hm)) != ACE_OK)
+    if ((st = launch(c, "cn_mfma_f64", k_cn_mfma<double, double>, grid, block, 0, A, lda, na, B,
+                     ldb, nb, K, s.kchunk, (cx<double>*)partial, hm)) != ACE_OK)
       return st;
   }
-  return launch(c, "reduce_partials", k_reduce_partials2<T>, dim3((na * nb + 63) / 64),
-                dim3(1024), 0, (const cx<T>*)partial, (int)s.ks, na, nb, alpha, C, ldc,
+  if (f64)
+    return launch(c, "reduce_partials", k_reduce_partials2<double>, dim3((na * nb + 63) / 64),
+                  dim3(1024), 0, (const cx<double>*)partial, (int)s.ks, na, nb, alpha, C, ldc,
+                  real_part ? 1 : 0, hm);
+  return launch(c, "reduce_partials", k_reduce_partials2<float>, dim3((na * nb + 63) / 64),
+                dim3(1024), 0, (const cx<float>*)partial, (int)s.ks, na, nb, alpha, C, ldc,
                 real_part ? 1 : 0, hm);
 }
 
@@ -816,9 +830,9 @@ ace_status gemm_nn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<double>
 }
 
 template ace_status gemm_cn<float>(ace_ctx, const cx<float>*, long, int, const cx<float>*, long,
-                                   int, long, double, cx<double>*, int, bool, bool, bool);
+                                   int, long, double, cx<double>*, int, CnMode, bool, bool);
 template ace_status gemm_cn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, long,
-                                    int, long, double, cx<double>*, int, bool, bool, bool);
+                                    int, long, double, cx<double>*, int, CnMode, bool, bool);
 template ace_status gemm_nn<float>(ace_ctx, const cx<float>*, long, int, const cx<double>*, int,
                                    int, cx<float>*, long, long, bool, bool);
 template ace_status gemm_nn<double>(ace_ctx, const cx<double>*, long, int, const cx<double>*, int,

@@ -54,6 +54,9 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
   if (n_occ < 1 || n_band < n_occ) return fail(c, ACE_E_ARG, "need 1 <= n_occ <= n_band");
   if (prec == ACE_REAL32 || prec == ACE_REAL64)
     return fail(c, ACE_E_UNSUPPORTED, "the tuner times the complex build");
+  if (stream_capturing(c))
+    return fail(c, ACE_E_CAPTURE, "the tuner allocates and synchronises");
+  if (!cache_path && !c->tune_cache.empty()) cache_path = c->tune_cache.c_str();
   const size_t eb = elem_bytes(prec);
   void* psi = nullptr;
   void* W = nullptr;
@@ -164,10 +167,10 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
   return ACE_OK;
 }
 
-ACE_EXPORT ace_status ace_tune_load(ace_ctx c, const char* cache_path) {
-  if (!c || !cache_path) return ACE_E_ARG;
+namespace ace {
+bool tune_cache_read(ace_ctx c, const char* cache_path) {
   FILE* f = fopen(cache_path, "r");
-  if (!f) return fail(c, ACE_E_ARG, "cannot open tuning cache");
+  if (!f) return false;
   // one setting per line: "n eb budget jblock [shape]" (shape 0 when absent)
   char line[256];
   while (fgets(line, sizeof line, f)) {
@@ -181,5 +184,12 @@ ACE_EXPORT ace_status ace_tune_load(ace_ctx c, const char* cache_path) {
       upsert(c, n, eb, bud, jb, shape);
   }
   fclose(f);
+  return true;
+}
+}  // namespace ace
+
+ACE_EXPORT ace_status ace_tune_load(ace_ctx c, const char* cache_path) {
+  if (!c || !cache_path) return ACE_E_ARG;
+  if (!tune_cache_read(c, cache_path)) return fail(c, ACE_E_ARG, "cannot open tuning cache");
   return ACE_OK;
 }

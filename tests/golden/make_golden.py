@@ -1,11 +1,15 @@
 """Writes the stored expected values under tests/golden/ from the FP64 oracle.
 
-Run from the repository root:  python tests/golden/make_golden.py
-Only the oracle and the seeded input generator are called.
+Run from the repository root:  python tests/golden/make_golden.py [small|full72|full64 ...]
+(no argument: all).  Only the oracle and the seeded input generator are called;
+the full-size cases split the oracle's W over columns j across worker
+processes (each worker calls the oracle's build_W for its own columns).
 """
 import json
+import multiprocessing as mp
 import os
 import sys
+import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -16,8 +20,11 @@ import oracle as O  # noqa: E402
 from paper_1601_07159_amd import synth  # noqa: E402
 
 
-def main():
-    here = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def small():
+    here = HERE
     psi = synth.smooth_orbitals(24, 10.0, 8, seed=0)
     g = O.Grid.cubic(24, 10.0)
     ge = O.Grid.cubic(24, 10.0, "erfc", 0.106)
@@ -47,6 +54,103 @@ def main():
     with open(os.path.join(here, "smooth48_seed0.json"), "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
+
+
+# -- full-size 72^3 screened case: 216 occupied of 256 smooth orbitals ----------
+N72, L72, NB72, NOCC72, MU72 = 72, 30.8, 256, 216, 0.106
+_shared = {}
+
+
+def _w_columns(args):
+    """Worker: columns j of W = V_X[phi] psi for one kernel setting (oracle)."""
+    g0, cols = args
+    psi = _shared["psi"]
+    g = O.Grid.cubic(N72, L72, "erfc", MU72, g0)
+    return g0, cols, O.build_W(psi[:NOCC72], psi, g, columns=cols)
+
+
+def _samples(shape, count, seed):
+    rng = np.random.default_rng(seed)
+    b = rng.integers(0, shape[0], count)
+    r = rng.integers(0, int(np.prod(shape[1:])), count)
+    return [int(x) for x in b], [int(x) for x in r]
+
+
+def full72(workers):
+    t0 = time.time()
+    psi = synth.smooth_orbitals(N72, L72, NB72, seed=0)
+    _shared["psi"] = psi
+    g0s = [0.0, np.pi / MU72 ** 2]
+    chunks = [list(range(j, min(j + 4, NB72))) for j in range(0, NB72, 4)]
+    Ws = {g0: np.empty_like(psi) for g0 in g0s}
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        for g0, cols, Wc in pool.imap_unordered(_w_columns, [(g0, c) for g0 in g0s for c in chunks]):
+            Ws[g0][cols] = Wc
+            print(f"full72: g0={g0:.3f} columns {cols[0]}..{cols[-1]} ({time.time() - t0:.0f} s)",
+                  flush=True)
+    out = {
+        "case": "72^3 grid, cubic L=30.8 bohr, 256 smooth orthonormal orbitals (Ecut 10 Ha, "
+                "seed 0); occupied = first 216; kernel erfc(mu r)/r with mu = 0.106 bohr^-1",
+        "n": N72, "L": L72, "n_band": NB72, "n_occ": NOCC72, "mu": MU72,
+    }
+    for g0 in g0s:
+        tag = "g0_0" if g0 == 0.0 else "g0_pi_over_mu2"
+        g = O.Grid.cubic(N72, L72, "erfc", MU72, g0)
+        W = Ws[g0]
+        M, L, xi = O.compress(psi, W, g)
+        out[f"g0_{tag}"] = float(g0)
+        out[f"E_X_trace_{tag}"] = O.exchange_energy_trace(M, NOCC72)
+        out[f"E_X_ace_{tag}"] = O.exchange_energy_ace(psi[:NOCC72], xi, g)
+        out[f"eig_minus_M_{tag}"] = [float(v) for v in np.linalg.eigvalsh(-M)]
+        out[f"M_diag_{tag}"] = [float(v) for v in np.real(np.diag(M))]
+        out[f"W_col_norm_{tag}"] = [float(v) for v in
+                                    np.sqrt(g.dV) * np.linalg.norm(W.reshape(NB72, -1), axis=1)]
+        out[f"xi_col_norm_{tag}"] = [float(v) for v in
+                                     np.sqrt(g.dV) * np.linalg.norm(xi.reshape(NB72, -1), axis=1)]
+        if g0 == 0.0:
+            # sampled entries of xi and of V_ACE X_t for X_t = generator(seed 100 + t)
+            b, r = _samples(psi.shape, 64, 7)
+            xf = xi.reshape(NB72, -1)
+            out["xi_samples"] = {"band": b, "point": r,
+                                 "re": [float(xf[i, k].real) for i, k in zip(b, r)],
+                                 "im": [float(xf[i, k].imag) for i, k in zip(b, r)]}
+            for t in (0, 19):
+                X = synth.smooth_orbitals(N72, L72, NB72, seed=100 + t)
+                Y = O.ace_apply(xi, X, g).reshape(NB72, -1)
+                b, r = _samples(psi.shape, 64, 200 + t)
+                out[f"apply_X{t}"] = {"seed": 100 + t, "band": b, "point": r,
+                                      "re": [float(Y[i, k].real) for i, k in zip(b, r)],
+                                      "im": [float(Y[i, k].imag) for i, k in zip(b, r)],
+                                      "fro": float(np.linalg.norm(Y))}
+                del X, Y
+        del M, L, xi
+        print(f"full72: {tag} done ({time.time() - t0:.0f} s)", flush=True)
+    with open(os.path.join(HERE, "smooth72_erfc_seed0.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
+def full64():
+    """64^3, L = 27 bohr, 128 smooth orbitals (seed 0): exchange energy of all 128."""
+    psi = synth.smooth_orbitals(64, 27.0, 128, seed=0)
+    g = O.Grid.cubic(64, 27.0)
+    out = {"case": "64^3 grid, cubic L=27 bohr, 128 smooth orthonormal orbitals (Ecut 10 Ha, "
+                   "seed 0), all occupied; Coulomb kernel, g0 = 0",
+           "E_X_coulomb_nocc128": O.exchange_energy_direct(psi, g)}
+    with open(os.path.join(HERE, "smooth64_seed0.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+
+
+def main():
+    which = sys.argv[1:] or ["small", "full64", "full72"]
+    if "small" in which:
+        small()
+    if "full64" in which:
+        full64()
+    if "full72" in which:
+        full72(int(os.environ.get("GOLDEN_WORKERS", "6")))
 
 
 if __name__ == "__main__":

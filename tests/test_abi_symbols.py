@@ -39,6 +39,8 @@ def test_every_declared_symbol_is_exported(lib):
 def test_status_strings_and_supported_sizes(lib):
     assert lib.ace_status_string(0) == b"ok"
     assert lib.ace_status_string(2) == b"matrix not positive definite"
+    assert lib.ace_status_string(6) == b"not allowed while the stream is being captured"
+    assert _lib.ACE_E_CAPTURE == 6
     buf = (ctypes.c_int * 32)()
     k = lib.ace_supported_n(buf, 32)
     sizes = [buf[i] for i in range(k)]
@@ -53,4 +55,4 @@ def test_null_context_is_an_argument_error(lib):
                             None) == 1
     assert lib.ace_apply(None, ctypes.byref(g), 0, None, 1, 1, None, 1, 1, None, 1) == 1
     assert lib.ace_destroy(None) == 1
-    assert lib.ace_create(None, None) == 1
+    assert lib.ace_create(None, None, None) == 1

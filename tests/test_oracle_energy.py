@@ -108,3 +108,26 @@ def test_golden_seeded_case():
     ge = O.Grid.cubic(24, 10.0, "erfc", 0.106)
     e2 = O.exchange_energy_direct(psi, ge)
     assert abs(e2 - gold["E_X_erfc_mu0.106"]) <= 1e-12 * abs(e2)
+
+
+def test_full_size_golden_is_self_consistent():
+    """The stored 72^3 values (written by the oracle over worker processes)
+    satisfy what the method fixes independently of how they were computed:
+    the trace and ACE forms of E_X agree, eig(-M) is positive, the g0 term is
+    the exact rank-N_occ shift E_X(g0) - E_X(0) = -g0 N_occ / (2 Omega) for
+    orthonormal orbitals (the G = 0 Fourier component of every pair density
+    conj(phi_i) phi_j is delta_ij / Omega), and tr(-M) equals the sum of the
+    stored eigenvalues and of minus the stored diagonal."""
+    with open(os.path.join(GOLDEN, "smooth72_erfc_seed0.json")) as f:
+        d = json.load(f)
+    omega = d["L"] ** 3
+    for tag in ("g0_0", "g0_pi_over_mu2"):
+        assert abs(d[f"E_X_trace_{tag}"] - d[f"E_X_ace_{tag}"]) <= 1e-12 * abs(d[f"E_X_trace_{tag}"])
+        eig = np.asarray(d[f"eig_minus_M_{tag}"])
+        assert np.all(eig > 0) and np.all(np.diff(eig) >= 0)
+        assert abs(eig.sum() + np.sum(d[f"M_diag_{tag}"])) <= 1e-12 * eig.sum()
+        assert len(eig) == d["n_band"] == len(d[f"W_col_norm_{tag}"])
+    g0 = d["g0_g0_pi_over_mu2"]
+    assert abs(g0 - np.pi / d["mu"] ** 2) <= 1e-12 * g0
+    shift = d["E_X_trace_g0_pi_over_mu2"] - d["E_X_trace_g0_0"]
+    assert abs(shift + g0 * d["n_occ"] / (2.0 * omega)) <= 1e-12 * abs(shift)
