@@ -168,6 +168,26 @@ ace_status ace_apply(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                      const void* X, int n_x, long ld_x, void* Y, long ld_y);
 
 /*
+ * Allocation-free variant of ace_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture on a context whose workspace
+ * was never sized, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, result and kernels as ace_apply; the scratch the kernels
+ * need (the n_band x n_x matrix dV xi^H X and the reduction's split-K partial
+ * sums) lives in a static device array of 48 MiB inside the library instead of
+ * the context workspace, so the call allocates nothing, never synchronises and
+ * never grows the workspace.  Each GPU that loads the library holds its own
+ * copy of the array until the process ends.  Limit: the scratch must fit the
+ * 48 MiB (n_band x n_x up to 256 x 256 at any supported grid and precision);
+ * larger sizes return ACE_E_UNSUPPORTED before anything is enqueued.  All
+ * calls on one GPU share that GPU's array: two calls that may overlap on one
+ * GPU (other contexts, or other streams not ordered after this one) race and
+ * must be serialised by the caller.
+ */
+ace_status ace_apply_noalloc(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                             const void* xi, int n_band, long ld_xi,
+                             const void* X, int n_x, long ld_x, void* Y, long ld_y);
+
+/*
  * Fock exchange energy of the n_occ orbitals phi, written to *ex_dev (one
  * device double).
  *  xi != NULL: E_X = -1/2 sum_{i,k} |<xi_k, phi_i>|^2   (Eq. EX_ACE, no Poisson solve)

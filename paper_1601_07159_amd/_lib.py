@@ -14,7 +14,7 @@ ACE_COULOMB, ACE_ERFC = 0, 1
 
 EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
-    "ace_apply", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
+    "ace_apply", "ace_apply_noalloc", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
     "ace_supported_n", "ace_build_batched", "ace_autotune", "ace_tune_load",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
@@ -51,6 +51,7 @@ _PROTOS = {
     "ace_build_W": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l, _d]),
     "ace_compress": (_i, [_vp, _gp, _i, _vp, _l, _vp, _l, _i, _vp, _l, _vp, _vp]),
     "ace_apply": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l]),
+    "ace_apply_noalloc": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp, _l]),
     "ace_exchange_energy": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _i, _l, _vp]),
     "ace_exchange_energy_grad": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _vp, _l]),
     "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),

@@ -78,6 +78,9 @@ bool stream_capturing(ace_ctx c);
 // Reads a tuning cache ("n eb budget jblock [shape]" per line) into the
 // context; a missing file returns false.
 bool tune_cache_read(ace_ctx c, const char* path);
+// Looks up, once per device and with that device current, the device address
+// of the allocation-free apply's static scratch array (noalloc.hip).
+void noalloc_setup(int device);
 
 #define ACE_TRY(x)               \
   do {                           \
@@ -101,7 +104,8 @@ struct GridInfo {
 // sets *st if a piece exceeds what ws_begin reserved.
 ace_status ws_begin(ace_ctx c, size_t total_bytes);
 void* ws_take(ace_ctx c, size_t bytes, ace_status* st);
-// Scratch bytes gemm_cn takes from the workspace for these sizes.
+// Scratch bytes gemm_cn takes from the workspace for these sizes (the most
+// over every arithmetic and the Hermitian shapes).
 size_t gemm_cn_scratch_bytes(int na, int nb, long K);
 
 // Blocking of the build: A occupied orbitals x B bands per pair block, or the
@@ -184,6 +188,9 @@ bool overlap(Span a, Span b);
 // BF16 hi/lo products with FP32 accumulation (complex64 only), kFp64 FP64 MFMA
 // products of complex64 data with FP64 accumulation.
 enum CnMode { kNative = 0, kBf16Split = 1, kFp64 = 2 };
+// Exact scratch bytes of one gemm_cn call (complex data of data_bytes per
+// element, arithmetic mode, Hermitian shape or not).
+size_t gemm_cn_partial_bytes(int na, int nb, long K, size_t data_bytes, CnMode mode, bool herm);
 // Mode of M for a precision.
 inline CnMode compress_mode(ace_prec p) {
   return (p == ACE_MIXED || p == ACE_REAL32) ? kBf16Split : p == ACE_FP32 ? kFp64 : kNative;

@@ -294,7 +294,7 @@ static ace_status apply_t(ace_ctx c, const GridInfo& g, const cx<T>* xi, int nb,
                           const cx<T>* X, int nx, long ldx, cx<T>* Y, long ldy,
                           bool real = false) {
   const size_t mat = align_up((size_t)nb * nx * sizeof(cx<double>), 256);
-  ACE_TRY(ws_begin(c, mat + gemm_cn_scratch_bytes(nb, nx, g.ng)));
+  ACE_TRY(ws_begin(c, mat + gemm_cn_partial_bytes(nb, nx, g.ng, sizeof(cx<T>), kNative, false)));
   ace_status st = ACE_OK;
   cx<double>* C = (cx<double>*)ws_take(c, mat, &st);
   if (!C) return st;
@@ -392,6 +392,7 @@ ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream, const char* tune_ca
           hipSuccess &&
       cus > 0)
     c->num_cus = cus;
+  noalloc_setup(c->device);  // device address of the allocation-free apply's scratch
   *out = c;
   return ACE_OK;
 }
@@ -584,10 +585,25 @@ ACE_EXPORT ace_status ace_compress(ace_ctx c, const ace_grid* grid, ace_prec pre
                               compress_mode(prec));
 }
 
+namespace ace {
+// The apply on the context workspace (sub == nullptr) or on a caller-provided
+// device arena [sub, sub + sub_bytes) that it never grows (sizes that need
+// more are refused before anything is enqueued).
+ace_status apply_entry(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* xi, int n_band,
+                       long ld_xi, const void* X, int n_x, long ld_x, void* Y, long ld_y,
+                       char* sub, size_t sub_bytes);
+}  // namespace ace
+
 ACE_EXPORT ace_status ace_apply(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* xi,
                                 int n_band, long ld_xi, const void* X, int n_x, long ld_x, void* Y,
                                 long ld_y) {
   if (!c) return ACE_E_ARG;
+  return apply_entry(c, grid, prec, xi, n_band, ld_xi, X, n_x, ld_x, Y, ld_y, nullptr, 0);
+}
+
+ace_status ace::apply_entry(ace_ctx c, const ace_grid* grid, ace_prec prec, const void* xi,
+                            int n_band, long ld_xi, const void* X, int n_x, long ld_x, void* Y,
+                            long ld_y, char* sub, size_t sub_bytes) {
   GridInfo g;
   ACE_TRY(check_grid(c, grid, prec, &g));
   ACE_TRY(check_block(c, xi, n_band, ld_xi, g, "xi"));
@@ -602,18 +618,41 @@ ACE_EXPORT ace_status ace_apply(ace_ctx c, const ace_grid* grid, ace_prec prec, 
     ACE_TRY(check_real_view(c, xi, ld_xi, eb, "xi"));
     ACE_TRY(check_real_view(c, X, ld_x, eb, "X"));
     ACE_TRY(check_real_view(c, Y, ld_y, eb, "Y"));
-    const GridInfo gh = half_view(g);
-    if (prec == ACE_REAL64)
-      return apply_t<double>(c, gh, (const cx<double>*)xi, n_band, ld_xi / 2,
-                             (const cx<double>*)X, n_x, ld_x / 2, (cx<double>*)Y, ld_y / 2, true);
-    return apply_t<float>(c, gh, (const cx<float>*)xi, n_band, ld_xi / 2, (const cx<float>*)X,
-                          n_x, ld_x / 2, (cx<float>*)Y, ld_y / 2, true);
   }
-  if (prec == ACE_FP64)
-    return apply_t<double>(c, g, (const cx<double>*)xi, n_band, ld_xi, (const cx<double>*)X, n_x,
-                           ld_x, (cx<double>*)Y, ld_y);
-  return apply_t<float>(c, g, (const cx<float>*)xi, n_band, ld_xi, (const cx<float>*)X, n_x, ld_x,
-                        (cx<float>*)Y, ld_y);
+  const GridInfo gv = is_real(prec) ? half_view(g) : g;
+  if (sub) {
+    // workspace of apply_t: the n_band x n_x matrix and the split-K partials
+    const size_t need = align_up((size_t)n_band * n_x * sizeof(cx<double>), 256) +
+                        gemm_cn_partial_bytes(n_band, n_x, gv.ng, is_real(prec) ? 2 * eb : eb,
+                                              kNative, false);
+    if (need > sub_bytes) {
+      char buf[160];
+      snprintf(buf, sizeof buf,
+               "n_band x n_x too large for the allocation-free apply: needs %zu bytes of "
+               "scratch, the library holds %zu", need, sub_bytes);
+      return fail(c, ACE_E_UNSUPPORTED, buf);
+    }
+    c->sub_base = sub;
+    c->sub_bytes = sub_bytes;
+  }
+  ace_status st;
+  if (prec == ACE_REAL64)
+    st = apply_t<double>(c, gv, (const cx<double>*)xi, n_band, ld_xi / 2, (const cx<double>*)X,
+                         n_x, ld_x / 2, (cx<double>*)Y, ld_y / 2, true);
+  else if (prec == ACE_REAL32)
+    st = apply_t<float>(c, gv, (const cx<float>*)xi, n_band, ld_xi / 2, (const cx<float>*)X, n_x,
+                        ld_x / 2, (cx<float>*)Y, ld_y / 2, true);
+  else if (prec == ACE_FP64)
+    st = apply_t<double>(c, gv, (const cx<double>*)xi, n_band, ld_xi, (const cx<double>*)X, n_x,
+                         ld_x, (cx<double>*)Y, ld_y);
+  else
+    st = apply_t<float>(c, gv, (const cx<float>*)xi, n_band, ld_xi, (const cx<float>*)X, n_x,
+                        ld_x, (cx<float>*)Y, ld_y);
+  if (sub) {
+    c->sub_base = nullptr;
+    c->sub_bytes = 0;
+  }
+  return st;
 }
 
 ACE_EXPORT ace_status ace_exchange_energy(ace_ctx c, const ace_grid* grid, ace_prec prec,

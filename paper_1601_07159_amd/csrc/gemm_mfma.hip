@@ -733,6 +733,17 @@ size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
   return align_up(b32 > b64 ? b32 : b64, 256);
 }
 
+size_t gemm_cn_partial_bytes(int na, int nb, long K, size_t data_bytes, CnMode mode, bool herm) {
+  const bool bf16_split = data_bytes == sizeof(cx<float>) && mode == kBf16Split;
+  const bool f64 = data_bytes == sizeof(cx<double>) || mode == kFp64;
+  const int max_waves = f64 ? 8 : bf16_split ? 12 : 16;
+  const int cu_waves = f64 ? 12 : bf16_split ? 12 : 16;
+  CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
+  if (herm && na == nb) herm_shape(na, K, max_waves, cu_waves, &s);
+  const size_t part_eb = f64 ? sizeof(cx<double>) : sizeof(cx<float>);
+  return align_up((size_t)s.ks * na * nb * part_eb, 256);
+}
+
 template <typename T>
 ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, long ldb, int nb,
                    long K, double alpha, cx<double>* C, int ldc, CnMode mode,
