@@ -176,6 +176,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--pair-budget", type=int, default=0,
                     help="bytes of pair spectra in flight (0 = library default)")
+    ap.add_argument("--fft-shape", type=int, default=0, choices=[0, 1, 4, 8, 16],
+                    help="line shape of the slab and plane passes (0 = library default)")
+    ap.add_argument("--accum-shape", type=int, default=0, choices=[0, 1, 16],
+                    help="form of the accumulate pass (0 = library default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="cfg4: skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -221,6 +225,10 @@ def main():
     ctx = ace.Context(0)
     if args.pair_budget:
         ctx.set_pair_budget(args.pair_budget)
+    if args.fft_shape:
+        ctx.set_tuning("fft_shape", args.fft_shape)
+    if args.accum_shape:
+        ctx.set_tuning("accum_shape", args.accum_shape)
     ctx.reserve(grid, prec, nocc, nband, nx)
 
     def make_bufs(dt):
@@ -550,7 +558,7 @@ def run_batched(args, cfg):
             same = sorted((sp for sp in specs if sp["n"] == n), key=lambda sp: sp["nocc"])
             med = same[len(same) // 2]
             r = ctx.autotune(ace.Grid.cubic(n, med["L"]), "fp32", med["nocc"], med["nband"])
-            tuned[n] = {k: r[k] for k in ("pair_budget", "jblock", "fft_shape")}
+            tuned[n] = {k: r[k] for k in ("pair_budget", "jblock", "fft_shape", "accum_shape")}
             log(f"bench: cfg4: autotuned n={n}: {tuned[n]} ({r['ms']:.2f} ms per build)")
     ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32", n_branches=nbr),
                      args.steps, args.warmup) * 1e3

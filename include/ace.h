@@ -256,19 +256,21 @@ ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_i
  * scratch orbitals (n_occ of n_band, allocated and freed here, so this call
  * allocates and synchronises) over candidate pair budgets (the number of pair
  * spectra in flight) and band blocks, then, at the fastest of those, over the
- * line shapes of the FFT passes (ACE_TUNE_FFT_SHAPE values 1, 4 and 8), and
+ * line shapes of the FFT passes (ACE_TUNE_FFT_SHAPE values 1, 4, 8 and 16) and
+ * then the forms of the accumulate pass (ACE_TUNE_ACCUM_SHAPE 1 and 16), and
  * keeps the fastest in the context; later builds of that grid size and
  * element size use it where the explicit knobs are not set.  cache_path
  * (nullable; NULL means the context's tune_cache, if any): the result is
- * appended as a text line "n element_bytes budget jblock shape".  Outputs (nullable): the choice (shape 0 = the defaults) and
- * its time per build in ms.  Complex precisions only (ACE_E_UNSUPPORTED for the
- * real ones).
+ * appended as a text line "n element_bytes budget jblock shape accum".
+ * Outputs (nullable): the choice (shape or accum 0 = the defaults) and its time
+ * per build in ms.  Complex precisions only (ACE_E_UNSUPPORTED for the real
+ * ones).
  */
 ace_status ace_autotune(ace_ctx ctx, const ace_grid* grid, ace_prec prec, int n_occ, int n_band,
                         const char* cache_path, long* best_budget, long* best_jblock,
-                        int* best_shape, double* best_ms);
+                        int* best_shape, int* best_accum, double* best_ms);
 /* Load tuning results written by ace_autotune (later lines win; a line
- * without the shape field reads as shape 0). */
+ * without the shape or accum field reads as 0 there). */
 ace_status ace_tune_load(ace_ctx ctx, const char* cache_path);
 
 /* Grid sizes n (per axis) compiled into this library; returns how many were
@@ -297,10 +299,14 @@ ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
  *  ACE_TUNE_FFT_SHAPE    line FFTs of the slab and plane passes: 1 one thread
  *                        per line, 4 a lane quad per line, 8 an octet of lanes
  *                        per line (grids whose n is a multiple of 8 from 16;
- *                        quads otherwise), 0 (default) automatic
+ *                        quads otherwise), 16 a line split over four lanes 16
+ *                        apart, 0 (default) automatic
+ *  ACE_TUNE_ACCUM_SHAPE  accumulate pass: 1 one thread per pencil (accumulator
+ *                        in LDS), 16 a pencil split over four lanes 16 apart
+ *                        (accumulator in registers), 0 (default) automatic
  * They change speed only; results agree to rounding. */
 enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2,
-       ACE_TUNE_FFT_SHAPE = 3 };
+       ACE_TUNE_FFT_SHAPE = 3, ACE_TUNE_ACCUM_SHAPE = 4 };
 ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
 ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
 

@@ -20,7 +20,8 @@ EXPORTED = [
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
     "ace_last_error",
 ]
-ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE = 0, 1, 2, 3
+(ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE,
+ ACE_TUNE_ACCUM_SHAPE) = 0, 1, 2, 3, 4
 
 
 class AceGrid(ctypes.Structure):
@@ -58,7 +59,8 @@ _PROTOS = {
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
     "ace_build_batched": (_i, [_vp, _i, _i, ctypes.POINTER(AceInstance), _i]),
     "ace_autotune": (_i, [_vp, _gp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_l),
-                          ctypes.POINTER(_l), ctypes.POINTER(_i), ctypes.POINTER(_d)]),
+                          ctypes.POINTER(_l), ctypes.POINTER(_i), ctypes.POINTER(_i),
+                          ctypes.POINTER(_d)]),
     "ace_tune_load": (_i, [_vp, ctypes.c_char_p]),
     "ace_profile_enable": (_i, [_vp, _i]),
     "ace_profile_reset": (_i, [_vp]),

@@ -24,7 +24,8 @@ from ._lib import ACE_FP32, ACE_FP64, ACE_MIXED, ACE_REAL32, ACE_REAL64  # noqa:
 PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED, "real64": ACE_REAL64,
         "real32": ACE_REAL32}
 _TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
-              "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE}
+              "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE,
+              "accum_shape": _lib.ACE_TUNE_ACCUM_SHAPE}
 
 
 class AceError(RuntimeError):
@@ -305,14 +306,15 @@ class Context:
         """Time the build over pair budgets, band blocks and FFT line shapes; keep
         the fastest for this grid size (ace_autotune)."""
         g = grid.as_c()
-        bud, jb, sh, ms = ctypes.c_long(), ctypes.c_long(), ctypes.c_int(), ctypes.c_double()
+        bud, jb, sh, ac = ctypes.c_long(), ctypes.c_long(), ctypes.c_int(), ctypes.c_int()
+        ms = ctypes.c_double()
         self._bind_stream()
         self._check(self._lib.ace_autotune(
             self._h, ctypes.byref(g), _prec(prec), int(n_occ), int(n_band),
             cache_path.encode() if cache_path else None, ctypes.byref(bud), ctypes.byref(jb),
-            ctypes.byref(sh), ctypes.byref(ms)))
+            ctypes.byref(sh), ctypes.byref(ac), ctypes.byref(ms)))
         return {"pair_budget": bud.value, "jblock": jb.value, "fft_shape": sh.value,
-                "ms": ms.value}
+                "accum_shape": ac.value, "ms": ms.value}
 
     def tune_load(self, cache_path: str):
         self._check(self._lib.ace_tune_load(self._h, cache_path.encode()))

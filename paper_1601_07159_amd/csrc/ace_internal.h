@@ -31,6 +31,7 @@ struct ace_ctx_s {
     long budget;
     long jblock;
     int shape;
+    int accum;  // form of the accumulate pass (0 = default)
   };
   std::vector<Tuned> tuned;
   unsigned tune_gen = 0;
@@ -43,7 +44,8 @@ struct ace_ctx_s {
   size_t pair_budget = 0;  // 0 = default
   long jblock = 0;         // band block of the build; 0 = automatic
   bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
-  int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread per line, 4 quad, 8 octet
+  int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread, 4 quad, 8 octet, 16 split
+  int accum_shape = 0;       // accumulate pass: 0 auto, 1 thread per pencil, 16 split lines
   int num_cus = 256;
   std::string last_error;
   std::string tune_cache;              // default cache file of ace_autotune ("" = none)

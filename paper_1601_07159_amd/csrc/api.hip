@@ -462,9 +462,14 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
     case ACE_TUNE_JBLOCK: c->jblock = value; return ACE_OK;
     case ACE_TUNE_SYMMETRY: c->use_symmetry = value != 0; return ACE_OK;
     case ACE_TUNE_FFT_SHAPE:
-      if (value != 0 && value != 1 && value != 4 && value != 8)
-        return fail(c, ACE_E_ARG, "fft shape 0, 1, 4 or 8");
+      if (value != 0 && value != 1 && value != 4 && value != 8 && value != 16)
+        return fail(c, ACE_E_ARG, "fft shape 0, 1, 4, 8 or 16");
       c->fft_shape = (int)value;
+      return ACE_OK;
+    case ACE_TUNE_ACCUM_SHAPE:
+      if (value != 0 && value != 1 && value != 16)
+        return fail(c, ACE_E_ARG, "accumulate shape 0, 1 or 16");
+      c->accum_shape = (int)value;
       return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
@@ -477,6 +482,7 @@ ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
     case ACE_TUNE_JBLOCK: *value = c->jblock; return ACE_OK;
     case ACE_TUNE_SYMMETRY: *value = c->use_symmetry ? 1 : 0; return ACE_OK;
     case ACE_TUNE_FFT_SHAPE: *value = c->fft_shape; return ACE_OK;
+    case ACE_TUNE_ACCUM_SHAPE: *value = c->accum_shape; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }

@@ -55,7 +55,7 @@ ace_status enqueue_instance(ace_ctx c, const ace_instance& in, const GridInfo& g
 
 std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_instance* inst,
                                     int nbr) {
-  std::vector<unsigned char> k(sizeof(ace_instance) * n + 64);
+  std::vector<unsigned char> k(sizeof(ace_instance) * n + 72);
   std::memcpy(k.data(), inst, sizeof(ace_instance) * n);
   unsigned char* t = k.data() + sizeof(ace_instance) * n;
   const void* ws = c->ws;
@@ -69,6 +69,7 @@ std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_i
   std::memcpy(t + 48, &symm, sizeof symm);
   std::memcpy(t + 52, &c->fft_shape, sizeof c->fft_shape);
   std::memcpy(t + 56, &c->tune_gen, sizeof c->tune_gen);
+  std::memcpy(t + 64, &c->accum_shape, sizeof c->accum_shape);
   return k;
 }
 

@@ -370,6 +370,133 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
   for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
 }
 
+// Split-line forms of the slab and plane passes: every line FFT is split over
+// 4 lanes 16 apart (fft_quad_* with lane distance 16: lane p + 16 h of wave w
+// holds part h of line l = 16 w + p), so 16 consecutive lanes hold the same
+// part of 16 consecutive lines and every global access of 16 lanes is one
+// contiguous row segment.  A workgroup of kRowWaves = ceil(N / 16) waves
+// handles an N x N slab or plane; lines l >= N (N = 8, 12, 24, 40, 72) are
+// idle: they take part in the lane exchanges on clamped data and store
+// nothing.  The coalesced flat loads and stores of the plane use the first 4 N
+// threads.  LDS rows are kRowLd(N) elements apart, an odd number, so that 16
+// lines at one offset fall in distinct banks.
+template <int N>
+constexpr int kRowWaves = (N + 15) / 16;
+template <int N>
+constexpr int kRowLd = N + 1 - (N & 1);
+
+// Forward slab pass: one workgroup per (x0 slab, pair).  The pair product
+// conj(phi_i) psi_j is formed while the slab is loaded (coalesced) into LDS;
+// 2-D FFT over axis 2 (rows) then axis 1 (columns); the column results go
+// straight to global memory, 16 lanes on consecutive columns.
+template <int N, typename T>
+__global__ __launch_bounds__(64 * kRowWaves<N>) void k_pair_fwd_slab_row(
+    const cx<T>* __restrict__ phi, long ldphi, const cx<T>* __restrict__ psi, long ldpsi,
+    cx<T>* __restrict__ buf, int mode, int i0, int A, int j0, long p0, int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kRowLd<N>;
+  constexpr int M = N / 4;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int x0 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)x0 * npairs);
+  int i, j;
+  pair_of(mode, i0, A, j0, p0, p, &i, &j);
+  const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
+  const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
+  const int t = threadIdx.x;
+  const int h = (t >> 4) & 3;
+  const int l = ((t >> 6) << 4) + (t & 15);
+  const bool live = l < N;
+  const int lc = live ? l : N - 1;
+  if (t < 4 * N) {
+    const int rr = t / N, cc = t - rr * N;  // element t + 4N q sits at row 4q + rr, column cc
+    cx<T> va[M], vb[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) va[q] = a[(4 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) vb[q] = b[(4 * q + rr) * N + cc];
+#pragma unroll
+    for (int q = 0; q < M; ++q) s[(4 * q + rr) * LD + cc] = cmulc(va[q], vb[q]);
+  }
+  __syncthreads();
+  cx<T> v[M];
+  // axis 2: row l (read and rewritten by its own four lanes only: one wave)
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[lc * LD + h + 4 * m];
+  fft_quad_d2b<N, -1, T, 16>(v, h);
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
+  }
+  __syncthreads();
+  // axis 1: column l
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[(h + 4 * m) * LD + lc];
+  fft_quad_d2b<N, -1, T, 16>(v, h);
+  if (!live) return;
+  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
+#pragma unroll
+  for (int k = 0; k < M; ++k) store_nt(&out[quad_block_index(k, M, h) * N], v[k]);
+}
+
+// Plane pass: one workgroup per (k1 plane, pair).  Along axis 0 (column l of
+// the plane, read straight from global memory): forward FFT, multiply by K',
+// inverse FFT; then through LDS the inverse FFT along axis 2 (row l); coalesced
+// store of the plane.
+template <int N, typename T>
+__global__ __launch_bounds__(64 * kRowWaves<N>) void k_plane_kernel_row(cx<T>* __restrict__ buf,
+                                                                   const T* __restrict__ Kt,
+                                                                   int npairs) {
+  constexpr int NN = N * N;
+  constexpr int LD = kRowLd<N>;
+  constexpr int M = N / 4;
+  __shared__ cx<T> s[N * LD];
+  const long lid = xcd_logical(blockIdx.x, gridDim.x);
+  if (lid >= (long)N * npairs) return;
+  const int k1 = (int)(lid / npairs);
+  const int p = (int)(lid - (long)k1 * npairs);
+  const int t = threadIdx.x;
+  const int h = (t >> 4) & 3;
+  const int l = ((t >> 6) << 4) + (t & 15);
+  const bool live = l < N;
+  const int lc = live ? l : N - 1;
+  cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
+  cx<T> v[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + lc];
+  fft_quad_d2b<N, -1, T, 16>(v, h);
+  const T* kcol = Kt + (size_t)k1 * N + lc;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T kk = kcol[(size_t)quad_block_index(k, M, h) * NN];
+    v[k].x *= kk;
+    v[k].y *= kk;
+  }
+  fft_quad_b2d<N, +1, T, 16>(v, h);
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) s[(h + 4 * m) * LD + l] = v[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = s[lc * LD + h + 4 * m];
+  fft_quad_d2b<N, +1, T, 16>(v, h);
+  // row l is read and rewritten by its own four lanes only (one wave, in
+  // order; idle lanes read a clamped row of their own wave)
+  if (live) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
+  }
+  __syncthreads();
+  if (t < 4 * N) {
+    const int rr = t / N, cc = t - rr * N;
+#pragma unroll
+    for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
+  }
+}
+
 // Octet forms of the slab and plane passes (N = 8 M lines over the 8 lanes of
 // an octet: 8N threads, line l = t / 8, lane h = t % 8).  LDS rows are kOctLd
 // apart with kOctLd = 2 (mod 16): a 16-lane phase of an 8-byte column access
@@ -939,19 +1066,24 @@ __global__ __launch_bounds__(256) void k_pencil_energy(const cx<T>* __restrict__
   const int p = blockIdx.x / TILES;
   const int tile = blockIdx.x - p * TILES;
   const int t = threadIdx.x;
-  const int h = t & 3;
-  const int q = tile * 64 + (t >> 2);
+  // pencil p_ + 16 (t >> 6) of the tile on lanes p_ + 16 h (split lines, 16
+  // consecutive pencils per row segment)
+  const int h = (t >> 4) & 3;
+  const int q = tile * 64 + ((t >> 6) << 4) + (t & 15);
   double sum = 0.0;
-  if (q < NN) {
-    const cx<T>* base = buf + (size_t)p * N * NN + q;
+  {
+    const int qc = q < NN ? q : NN - 1;  // the lanes of a pencil past the end stay in step
+    const cx<T>* base = buf + (size_t)p * N * NN + qc;
     cx<T> v[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) v[m] = base[(size_t)(h + 4 * m) * NN];
-    fft_quad_d2b<N, -1, T>(v, h);
+    fft_quad_d2b<N, -1, T, 16>(v, h);
+    if (q < NN) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const double kk = (double)Kt[(size_t)quad_block_index(k, M, h) * NN + q];
-      sum += kk * ((double)v[k].x * v[k].x + (double)v[k].y * v[k].y);
+      for (int k = 0; k < M; ++k) {
+        const double kk = (double)Kt[(size_t)quad_block_index(k, M, h) * NN + q];
+        sum += kk * ((double)v[k].x * v[k].x + (double)v[k].y * v[k].y);
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
@@ -1137,12 +1269,16 @@ ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
                 g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
 }
 
-// Line shape of the slab and plane passes: one thread per line or a quad per
-// line (far fewer registers: no spills for FP64 at large N, occupancy 4
-// instead of 1 for FP32 at N >= 64).  Defaults from timings on the MI355X:
-// slab pass quad from N = 72 (FP32) or 64 (FP64), plane pass quad from
-// N = 64 (FP32) or 48 (FP64).  The tuning knob ACE_TUNE_FFT_SHAPE overrides
-// both passes (1 = thread, 4 = quad, 8 = octet), else an autotuned shape for
+// Line shape of the slab and plane passes: one thread per line (1), a lane
+// quad per line with DPP exchanges (4), an octet (8), or a line split over
+// lanes 16 apart with permlane exchanges (16).  Defaults from timings on the
+// MI355X: slab pass quad from N = 72 (FP32) or 64 (FP64), plane pass quad from
+// N = 64 (FP32) or 48 (FP64), one thread per line below.  The split form keeps
+// 16-lane accesses contiguous but pays two VALU instructions per exchanged
+// word where a DPP quad permutation rides on the consuming instruction: at
+// N = 72 it measured slower (slab 2.07 -> 2.72 ms, plane 2.3 -> 3.7 ms per
+// 1,146 pairs), at N = 48 too, so it is used only when asked for.  The tuning
+// knob ACE_TUNE_FFT_SHAPE overrides both passes, else an autotuned shape for
 // this grid size and element size.
 int line_shape(ace_ctx c, int n, int eb) {
   if (c->fft_shape) return c->fft_shape;
@@ -1152,12 +1288,16 @@ int line_shape(ace_ctx c, int n, int eb) {
 }
 
 template <int N, typename T>
-bool use_quad(ace_ctx c, bool plane_pass) {
+constexpr bool kOctOk = N % 8 == 0 && N >= 16;
+
+// Form of the slab (plane_pass false) or plane pass: 1, 4, 8 or 16 as above.
+template <int N, typename T>
+int pass_form(ace_ctx c, bool plane_pass) {
   const int sh = line_shape(c, N, (int)sizeof(cx<T>));
-  if (sh == 1) return false;
-  if (sh == 4 || sh == 8) return true;
-  if (sizeof(T) == 8) return plane_pass ? N >= 48 : N >= 64;
-  return plane_pass ? N >= 64 : N >= 72;
+  if (sh == 8) return kOctOk<N, T> ? 8 : 4;
+  if (sh == 1 || sh == 4 || sh == 16) return sh;
+  if (sizeof(T) == 8) return (plane_pass ? N >= 48 : N >= 64) ? 4 : 1;
+  return (plane_pass ? N >= 64 : N >= 72) ? 4 : 1;
 }
 
 // Octet lines (N a multiple of 8 from 16) only on request (knob value 8):
@@ -1166,21 +1306,18 @@ bool use_quad(ace_ctx c, bool plane_pass) {
 // as the third exchange, the per-lane twiddles and the 64-byte row segments
 // of the plane's column loads cost more than the full waves gain.
 template <int N, typename T>
-constexpr bool kOctOk = N % 8 == 0 && N >= 16;
-template <int N, typename T>
-bool use_oct(ace_ctx c) {
-  return kOctOk<N, T> && line_shape(c, N, (int)sizeof(cx<T>)) == 8;
-}
-
-template <int N, typename T>
-ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx<T>* psi,
-                    long ldpsi, cx<T>* buf, int mode, int i0, int A, int j0, long p0, int np) {
+ace_status fwd_slab(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* psi, long ldpsi,
+                    cx<T>* buf, int mode, int i0, int A, int j0, long p0, int np) {
   const dim3 grid(xcd_pad((long)N * np));
+  const int form = pass_form<N, T>(c, false);
   if constexpr (kOctOk<N, T>)
-    if (use_oct<N, T>(c))
+    if (form == 8)
       return launch(c, "pair_fwd_slab", k_pair_fwd_slab_oct<N, T>, grid, dim3(8 * N), 0, phi,
                     ldphi, psi, ldpsi, buf, mode, i0, A, j0, p0, np);
-  if (quad)
+  if (form == 16)
+    return launch(c, "pair_fwd_slab", k_pair_fwd_slab_row<N, T>, grid, dim3(64 * kRowWaves<N>), 0,
+                  phi, ldphi, psi, ldpsi, buf, mode, i0, A, j0, p0, np);
+  if (form == 4)
     return launch(c, "pair_fwd_slab", k_pair_fwd_slab<N, T>, grid, dim3(4 * N), 0, phi, ldphi, psi,
                   ldpsi, buf, mode, i0, A, j0, p0, np);
   constexpr int P = t1_group<N, T>(40 * 1024);
@@ -1190,25 +1327,42 @@ ace_status fwd_slab(ace_ctx c, bool quad, const cx<T>* phi, long ldphi, const cx
 }
 
 template <int N, typename T>
-ace_status plane(ace_ctx c, bool quad, cx<T>* buf, const T* Kt, int np) {
+ace_status plane(ace_ctx c, cx<T>* buf, const T* Kt, int np) {
   const dim3 grid(xcd_pad((long)N * np));
+  const int form = pass_form<N, T>(c, true);
   if constexpr (kOctOk<N, T>)
-    if (use_oct<N, T>(c))
+    if (form == 8)
       return launch(c, "plane_kernel", k_plane_kernel_oct<N, T>, grid, dim3(8 * N), 0, buf, Kt,
                     np);
-  if (quad)
+  if (form == 16)
+    return launch(c, "plane_kernel", k_plane_kernel_row<N, T>, grid, dim3(64 * kRowWaves<N>), 0,
+                  buf, Kt, np);
+  if (form == 4)
     return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, Kt, np);
   constexpr int P = t1_group<N, T>(80 * 1024);
   return launch(c, "plane_kernel", k_plane_kernel_t1<N, T, P>,
                 dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, buf, Kt, np);
 }
 
-// Accumulate pass: the quad form by default; one thread per pencil (LDS
-// accumulator) when the line-shape knob asks for one thread per line.
+// Form of the accumulate pass: one thread per pencil with the accumulator in
+// LDS (1), or pencils split over lanes 16 apart with register accumulators
+// (16).  Measured per build (FP32): 48^3 split 0.92 ms vs LDS 1.03 ms
+// (5,120 pairs), 64^3 0.90 vs 0.90, 72^3 1.11 vs 0.95 ms per launch (the
+// split form needs 226 registers there, two waves per SIMD, and the permlane
+// exchanges add VALU work): split up to N = 64, LDS above.  The knob
+// ACE_TUNE_ACCUM_SHAPE overrides it, else an autotuned form.
+template <int N, typename T>
+int accum_form(ace_ctx c) {
+  if (c->accum_shape) return c->accum_shape;
+  for (const auto& t : c->tuned)
+    if (t.n == N && t.eb == (int)sizeof(cx<T>) && t.accum) return t.accum;
+  return N <= 64 ? 16 : 1;
+}
+
 template <int N, typename T>
 ace_status accum(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* buf, cx<T>* W, long ldW,
                  int i0, int A, int j0, int nbc, int accumulate, int mode) {
-  if (line_shape(c, N, (int)sizeof(cx<T>)) == 1) {
+  if (accum_form<N, T>(c) == 1) {
     constexpr int TILES = (N * N + 63) / 64;
     return launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nbc)),
                   dim3(64), 0, phi, ldphi, buf, W, ldW, i0, A, j0, nbc, accumulate, mode);
@@ -1236,24 +1390,23 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
   if (!Kt || !buf) return st;
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
-  const bool quad = use_quad<N, T>(c, false), quad_p = use_quad<N, T>(c, true);
   int jstart = 0;
   if (pl.merged) {
     const long all = (long)nocc * (nocc + 1) / 2 + (long)nocc * (nband - nocc);
-    if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 3, 0, nocc, nocc, 0L,
+    if ((st = fwd_slab<N, T>(c, phi, ldphi, psi, ldpsi, buf, 3, 0, nocc, nocc, 0L,
                              (int)all)) != ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)all)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, Kt, (int)all)) != ACE_OK) return st;
     return accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nband, 0, 3);
   }
   if (sym && pl.symblk == 0) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
     // accumulates all i from it (u_ij = conj(u_ji))
     const long tri = (long)nocc * (nocc + 1) / 2;
-    if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) !=
+    if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) !=
         ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, quad_p, buf, Kt, (int)tri)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, Kt, (int)tri)) != ACE_OK) return st;
     if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nocc, 0, 1)) != ACE_OK)
       return st;
     jstart = nocc;
@@ -1268,20 +1421,20 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
         const int j0 = J * b, nj = std::min(b, nocc - j0);
         if (I == J) {
           const int np = ni * (ni + 1) / 2;
-          if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 1, i0, 1, i0, 0L, np)) !=
+          if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, i0, 1, i0, 0L, np)) !=
               ACE_OK)
             return st;
-          if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
+          if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
           if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, i0, ni, (int)started[I], 1)) !=
               ACE_OK)
             return st;
           started[I] = 1;
         } else {
           const int np = ni * nj;
-          if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, phi, ldphi, buf, 0, i0, ni, j0, 0L, np)) !=
+          if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 0, i0, ni, j0, 0L, np)) !=
               ACE_OK)
             return st;
-          if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
+          if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
           // bands of J from the orbitals of I, then bands of I from those of J
           if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, j0, nj, (int)started[J], 0)) !=
               ACE_OK)
@@ -1300,10 +1453,10 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
     for (int i0 = 0; i0 < nocc; i0 += A) {
       const int Ac = std::min(A, nocc - i0);
       const int np = Ac * Bc;
-      if ((st = fwd_slab<N, T>(c, quad, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) !=
+      if ((st = fwd_slab<N, T>(c, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) !=
           ACE_OK)
         return st;
-      if ((st = plane<N, T>(c, quad_p, buf, Kt, np)) != ACE_OK) return st;
+      if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
       if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, Ac, j0, Bc, i0 > 0 ? 1 : 0, 0)) !=
           ACE_OK)
         return st;
@@ -1330,13 +1483,12 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
   cx<T>* buf = (cx<T>*)ws_take(c, pl.pairs_alloc * unit_bytes, &st);
   if (!Kt || !buf) return st;
   if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
-  const bool quad_p = use_quad<N, T>(c, true);
   if (pl.sym) {
     const int G = (nocc + 1) / 2, nu = (int)pl.pairs_alloc;
     if ((st = launch(c, "pair_fwd_real", k_pair_fwd_real_t1<N, T>, dim3(xcd_pad((long)N * nu)),
                      dim3(N), 0, phi, ldphi, psi, ldpsi, buf, 0, nocc, G, nocc, nu, 1)) != ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, quad_p, buf, Kt, nu)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, Kt, nu)) != ACE_OK) return st;
     const int nrows = G + (nband - nocc);
     return launch(c, "pencil_accum_real", k_pencil_accum_real_sym<N, T>,
                   dim3(xcd_pad((long)TILES * nrows)), dim3(64), 0, phi, ldphi, (const cx<T>*)buf,
@@ -1352,7 +1504,7 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
                        dim3(xcd_pad((long)N * nu)), dim3(N), 0, phi, ldphi, psi, ldpsi, buf, i0,
                        Ac, Am, j0, nu, 0)) != ACE_OK)
         return st;
-      if ((st = plane<N, T>(c, quad_p, buf, Kt, nu)) != ACE_OK) return st;
+      if ((st = plane<N, T>(c, buf, Kt, nu)) != ACE_OK) return st;
       if ((st = launch(c, "pencil_accum_real", k_pencil_accum_real<N, T>,
                        dim3(xcd_pad((long)TILES * Bc)), dim3(64), 0, phi, ldphi,
                        (const cx<T>*)buf, W, ldW, i0, Ac, Am, j0, Bc, i0 > 0 ? 1 : 0)) != ACE_OK)
@@ -1381,7 +1533,7 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
   for (long p0 = 0; p0 < total; p0 += chunk) {
     const int np = (int)std::min(chunk, total - p0);
-    if ((st = fwd_slab<N, T>(c, use_quad<N, T>(c, false), phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
+    if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
                              np)) != ACE_OK)
       return st;
     if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(256), 0,

@@ -28,16 +28,17 @@ __global__ __launch_bounds__(256) void k_fill_scratch(cx<T>* x, int n, int count
   x[idx] = {T(cos(ph) * (1.0 + 0.1 * b)), T(sin(ph))};
 }
 
-void upsert(ace_ctx c, int n, int eb, long budget, long jblock, int shape) {
+void upsert(ace_ctx c, int n, int eb, long budget, long jblock, int shape, int accum) {
   ++c->tune_gen;
   for (auto& t : c->tuned)
     if (t.n == n && t.eb == eb) {
       t.budget = budget;
       t.jblock = jblock;
       t.shape = shape;
+      t.accum = accum;
       return;
     }
-  c->tuned.push_back({n, eb, budget, jblock, shape});
+  c->tuned.push_back({n, eb, budget, jblock, shape, accum});
 }
 
 }  // namespace
@@ -47,7 +48,8 @@ using namespace ace;
 
 ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec prec, int n_occ,
                                    int n_band, const char* cache_path, long* best_budget,
-                                   long* best_jblock, int* best_shape, double* best_ms) {
+                                   long* best_jblock, int* best_shape, int* best_accum,
+                                   double* best_ms) {
   if (!c) return ACE_E_ARG;
   GridInfo g;
   ACE_TRY(check_grid(c, grid, prec, &g));
@@ -77,6 +79,7 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
   const size_t save_budget = c->pair_budget;
   const long save_jblock = c->jblock;
   const int save_shape = c->fft_shape;
+  const int save_accum = c->accum_shape;
   const bool save_prof = c->profiling;
   c->profiling = false;
   const long budgets[] = {256L << 20, 512L << 20, 1L << 30, 2L << 30, 4L << 30, 8L << 30};
@@ -128,7 +131,7 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
     }
   }
   // line shapes at the chosen blocking (0, the defaults, was timed above)
-  const int shapes[] = {1, 4, 8};
+  const int shapes[] = {1, 4, 8, 16};
   c->pair_budget = (size_t)bb;
   c->jblock = bj;
   for (int sh : shapes) {
@@ -142,27 +145,44 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
       bs = sh;
     }
   }
+  // accumulate-pass forms at the chosen blocking and line shape (0, the
+  // default, was timed above)
+  const int accums[] = {1, 16};
+  int ba = 0;
+  c->fft_shape = bs;
+  for (int af : accums) {
+    if (st != ACE_OK) break;
+    c->accum_shape = af;
+    const double ms = time_build();
+    if (ms < 0) break;
+    if (ms < best) {
+      best = ms;
+      ba = af;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->pair_budget = save_budget;
   c->jblock = save_jblock;
   c->fft_shape = save_shape;
+  c->accum_shape = save_accum;
   c->profiling = save_prof;
   hipStreamSynchronize(c->stream);
   hipFree(psi);
   hipFree(W);
   if (st != ACE_OK) return st;
-  upsert(c, g.n, (int)eb, bb, bj, bs);
+  upsert(c, g.n, (int)eb, bb, bj, bs, ba);
   if (cache_path) {
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "%d %d %ld %ld %d\n", g.n, (int)eb, bb, bj, bs);
+      fprintf(f, "%d %d %ld %ld %d %d\n", g.n, (int)eb, bb, bj, bs, ba);
       fclose(f);
     }
   }
   if (best_budget) *best_budget = bb;
   if (best_jblock) *best_jblock = bj;
   if (best_shape) *best_shape = bs;
+  if (best_accum) *best_accum = ba;
   if (best_ms) *best_ms = best;
   return ACE_OK;
 }
@@ -176,12 +196,15 @@ bool tune_cache_read(ace_ctx c, const char* cache_path) {
   while (fgets(line, sizeof line, f)) {
     int n, eb, shape = 0;
     long bud, jb;
-    const int got = sscanf(line, "%d %d %ld %ld %d", &n, &eb, &bud, &jb, &shape);
+    int accum = 0;
+    const int got = sscanf(line, "%d %d %ld %ld %d %d", &n, &eb, &bud, &jb, &shape, &accum);
     if (got < 4) continue;
     if (got == 4) shape = 0;
+    if (got <= 5) accum = 0;
     if (n > 0 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0 &&
-        (shape == 0 || shape == 1 || shape == 4 || shape == 8))
-      upsert(c, n, eb, bud, jb, shape);
+        (shape == 0 || shape == 1 || shape == 4 || shape == 8 || shape == 16) &&
+        (accum == 0 || accum == 1 || accum == 16))
+      upsert(c, n, eb, bud, jb, shape, accum);
   }
   fclose(f);
   return true;

@@ -40,14 +40,16 @@ def test_build_W_matches_oracle(ace, prec, n, L, nocc, nband, kind, mu, g0):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("shape", [1, 4, 8])
+@pytest.mark.parametrize("shape,accum", [(1, 1), (4, 16), (8, 1), (16, 16), (1, 16), (16, 1)])
 @pytest.mark.parametrize("n,L", [(12, 5.0), (16, 6.0), (24, 10.0), (32, 13.0), (40, 17.0),
                                  (48, 20.5), (64, 27.0), (72, 30.8)])
-def test_build_W_line_shapes(ace, prec, shape, n, L):
-    # every line form of the slab and plane passes (one thread, a quad or an
-    # octet of lanes per line; octets need n divisible by 8 from 16, quads
-    # stand in below) on the symmetric merged path and the rectangle path
-    print(f"build_W shape={shape} prec={prec} n={n}", flush=True)
+def test_build_W_line_shapes(ace, prec, shape, accum, n, L):
+    # every line form of the slab and plane passes (one thread, a quad, an
+    # octet or four lanes 16 apart per line; octets need n divisible by 8 from
+    # 16, quads stand in below) and both forms of the accumulate pass (one
+    # thread per pencil, split pencils) on the symmetric merged path and the
+    # rectangle path; the direct energy's split-pencil pass with them
+    print(f"build_W shape={shape} accum={accum} prec={prec} n={n}", flush=True)
     nocc, nband = 2, 3
     psi = synth.smooth_orbitals(n, L, nband, seed=7 * n + shape)
     g = ogrid(n, L, "erfc", 0.3)
@@ -55,6 +57,7 @@ def test_build_W_line_shapes(ace, prec, shape, n, L):
     ref = O.build_W(psi[:nocc], psi, g)
     ctx = ace.Context()
     ctx.set_tuning("fft_shape", shape)
+    ctx.set_tuning("accum_shape", accum)
     x = to_gpu(psi, prec)
     W_sym = to_np(ctx.build_W(x[:nocc], x, gg, prec))
     W_rect = to_np(ctx.build_W(x[:nocc].clone(), x, gg, prec))

@@ -23,10 +23,12 @@ def test_autotune_choice_persists_and_builds_match_oracle(tmp_path, prec):
     cache = str(tmp_path / "tune.txt")
     ctx = ace.Context()
     r = ctx.autotune(gg, prec, nocc, nband, cache_path=cache)
-    assert r["fft_shape"] in (0, 1, 4, 8)
+    assert r["fft_shape"] in (0, 1, 4, 8, 16)
+    assert r["accum_shape"] in (0, 1, 16)
     assert r["pair_budget"] > 0 and r["jblock"] >= 0 and r["ms"] > 0
     fields = open(cache).read().split()
-    assert len(fields) == 5 and int(fields[0]) == n and int(fields[4]) == r["fft_shape"]
+    assert len(fields) == 6 and int(fields[0]) == n and int(fields[4]) == r["fft_shape"]
+    assert int(fields[5]) == r["accum_shape"]
     x = to_gpu(psi, prec)
     W = to_np(ctx.build_W(x[:nocc], x, gg, prec))
     ctx.close()
