@@ -273,6 +273,14 @@ __global__ __launch_bounds__(N * P) void k_plane_kernel_t1(cx<T>* __restrict__ b
 // column reads ((h + 4m) LD + l) alike.
 template <int N>
 constexpr int kQuadLd = N + ((4 - N % 16) + 16) % 16;
+// Whether the quad forms stage their strided global accesses through LDS (the
+// plane's column loads, the slab's spectrum stores) so that every access
+// instruction covers whole rows: measured at N = 64 (plane pass 1.33 -> 1.23
+// ms per 640 pairs), but at N = 72, whose 48 KiB plane leaves 4.5 waves per
+// workgroup and three workgroups per CU, the two extra barriers cost more
+// (plane 2.33 -> 3.33 ms, slab 2.08 -> 2.44 ms per 1,146 pairs).
+template <int N>
+constexpr bool kQuadStage = N <= 64;
 
 // Forward slab pass: one workgroup per (x0 slab, pair).  The pair product
 // conj(phi_i) psi_j is formed while the slab is loaded (coalesced) into LDS;
@@ -320,9 +328,22 @@ __global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict
 #pragma unroll
   for (int m = 0; m < M; ++m) v[m] = s[(h + 4 * m) * LD + l];
   fft_quad_d2b<N, -1, T>(v, h);
-  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
+  if constexpr (kQuadStage<N>) {
+    // the spectrum slab leaves through LDS, so that every store instruction
+    // writes whole rows (a quad's direct stores cover 4 rows x 4 values per
+    // 16 lanes)
+    __syncthreads();
 #pragma unroll
-  for (int k = 0; k < M; ++k) store_nt(&out[quad_block_index(k, M, h) * N], v[k]);
+    for (int k = 0; k < M; ++k) s[quad_block_index(k, M, h) * LD + l] = v[k];
+    __syncthreads();
+    cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
+#pragma unroll
+    for (int q = 0; q < M; ++q) store_nt(&out[(4 * q + rr) * N + cc], s[(4 * q + rr) * LD + cc]);
+  } else {
+    cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN + l;
+#pragma unroll
+    for (int k = 0; k < M; ++k) store_nt(&out[quad_block_index(k, M, h) * N], v[k]);
+  }
 }
 
 // Plane pass: one workgroup per (k1 plane, pair).  Along axis 0 (column l of
@@ -343,9 +364,26 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
   const int t = threadIdx.x;
   const int l = t >> 2, h = t & 3;
   cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
+  const int rr = t / N, cc = t - rr * N;  // element t + 4N q sits at row 4q + rr, column cc
   cx<T> v[M];
+  if constexpr (kQuadStage<N>) {
+    // the plane comes in through LDS, so that every load instruction reads
+    // whole rows (a quad's direct column loads cover 4 rows x 4 values per
+    // 16 lanes)
+    {
+      cx<T> w[M];
 #pragma unroll
-  for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + l];
+      for (int q = 0; q < M; ++q) w[q] = plane[(size_t)(4 * q + rr) * NN + cc];
+#pragma unroll
+      for (int q = 0; q < M; ++q) s[(4 * q + rr) * LD + cc] = w[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = s[(h + 4 * m) * LD + l];
+  } else {
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + l];
+  }
   fft_quad_d2b<N, -1, T>(v, h);
   const T* kcol = Kt + (size_t)k1 * N + l;
 #pragma unroll
@@ -355,6 +393,7 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
     v[k].y *= kk;
   }
   fft_quad_b2d<N, +1, T>(v, h);
+  if constexpr (kQuadStage<N>) __syncthreads();  // every column read before any is rewritten
 #pragma unroll
   for (int m = 0; m < M; ++m) s[(h + 4 * m) * LD + l] = v[m];
   __syncthreads();
@@ -365,7 +404,6 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
 #pragma unroll
   for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
   __syncthreads();
-  const int rr = t / N, cc = t - rr * N;
 #pragma unroll
   for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
 }
