@@ -227,6 +227,47 @@ ace_status ace_orthonormalize(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
                               int* info_dev);
 
 /*
+ * Hamiltonian application for the linear eigenvalue problem of the inner
+ * iterations (Section 2, Eq. HFlineig, with a fixed local potential standing
+ * for V_ion + V_H; Alg. 1 applies V_X[phi] directly, Alg. 2 applies V_ACE):
+ *   Y = -1/2 Laplacian X + V_loc X + V_ex X,
+ *   V_ex = V_ACE = -xi (dV xi^H .)   when xi != NULL (n_xi vectors),
+ *          scale_x V_X[phi]            when phi != NULL (n_phi orbitals; the
+ *                                      pair solves of ace_build_W),
+ *          0                           when both are NULL (not both non-NULL).
+ * The Laplacian is spectral on the periodic grid: -1/2 Laplacian x =
+ * ifftn(|G|^2/2 fftn(x)) with G = 2 pi m / L per axis (the same G as the
+ * exchange kernel).  vloc (nullable): N_g reals in C order, double for ACE_FP64,
+ * float for ACE_FP32 / ACE_MIXED.  Complex precisions only.  Y must not overlap
+ * X, xi or phi.
+ */
+ace_status ace_apply_h(ace_ctx ctx, const ace_grid* grid, ace_prec prec, const void* vloc,
+                       const void* xi, int n_xi, long ld_xi,
+                       const void* phi, int n_phi, long ld_phi, double scale_x,
+                       const void* X, int n_x, long ld_x, void* Y, long ld_y);
+
+/*
+ * D = a A + b B + c C on blocks of n orbitals (real coefficients; B and C
+ * nullable, their terms then absent): the vector updates of polynomial
+ * filters in the eigensolver.  D may be A, B or C itself (same ld).
+ */
+ace_status ace_combine(ace_ctx ctx, const ace_grid* grid, ace_prec prec, int n,
+                       double a, const void* A, long ld_a, double b, const void* B, long ld_b,
+                       double c, const void* C, long ld_c, void* D, long ld_d);
+
+/*
+ * Rayleigh-Ritz step on span(X) for the linear eigenvalue problem (Eq.
+ * HFlineig): S = dV X^H (HX) (n x n, FP64 products, made Hermitian),
+ * S = Q diag(e) Q^H with e ascending (parallel cyclic Jacobi in FP64,
+ * n <= 512), Xout = X Q, HXout = (HX) Q (nullable), evals_dev = e (n device
+ * doubles).  X should be orthonormal (<x_a, x_b> = delta_ab) and HX = H X.
+ * The outputs must not overlap the inputs or each other.
+ */
+ace_status ace_rayleigh_ritz(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
+                             const void* X, long ld_x, const void* HX, long ld_hx, int n,
+                             void* Xout, void* HXout, long ld_out, double* evals_dev);
+
+/*
  * Batched build (Section 3 for many independent systems): for every instance,
  * W = scale * V_X[phi] psi as ace_build_W, then (when xi != NULL) the
  * compression of ace_compress with L not returned and the pivot status in

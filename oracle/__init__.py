@@ -16,6 +16,8 @@ Comput. 2016) for a reader to check by eye:
 * V_ACE = -xi xi^H                                      Section 3, Eq. (ACE)
 * E_X directly and from the projection vectors           Eqs. (EX), (EX_ACE)
 * oversampling N_band > N_occ                            end of Section 3
+* the self-consistent loops around the exchange          Alg. 1 (V_X), Alg. 2 (V_ACE),
+  operator with a linear eigensolver (oracle.scf_oracle)  Eq. (HFlineig)
 
 Pins against facts fixed outside this package live in tests/test_oracle_*.py.
 """

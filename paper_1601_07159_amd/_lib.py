@@ -18,7 +18,7 @@ EXPORTED = [
     "ace_supported_n", "ace_build_batched", "ace_autotune", "ace_tune_load",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
-    "ace_last_error",
+    "ace_last_error", "ace_apply_h", "ace_combine", "ace_rayleigh_ritz",
 ]
 (ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE,
  ACE_TUNE_ACCUM_SHAPE) = 0, 1, 2, 3, 4
@@ -70,6 +70,9 @@ _PROTOS = {
     "ace_set_pair_budget": (_i, [_vp, _l]),
     "ace_set_tuning": (_i, [_vp, _i, _l]),
     "ace_get_tuning": (_i, [_vp, _i, ctypes.POINTER(_l)]),
+    "ace_apply_h": (_i, [_vp, _gp, _i, _vp, _vp, _i, _l, _vp, _i, _l, _d, _vp, _i, _l, _vp, _l]),
+    "ace_combine": (_i, [_vp, _gp, _i, _i, _d, _vp, _l, _d, _vp, _l, _d, _vp, _l, _vp, _l]),
+    "ace_rayleigh_ritz": (_i, [_vp, _gp, _i, _vp, _l, _vp, _l, _i, _vp, _vp, _l, _vp]),
     "ace_status_string": (ctypes.c_char_p, [_i]),
     "ace_last_error": (ctypes.c_char_p, [_vp]),
 }

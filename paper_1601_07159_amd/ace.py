@@ -267,6 +267,69 @@ class Context:
                                                  ip))
         return out
 
+    def apply_h(self, X, grid: Grid, prec, vloc=None, xi=None, phi=None, scale_x: float = 1.0,
+                out=None):
+        """Y = (-1/2 Laplacian + V_loc) X + V_ex X with V_ex = V_ACE (xi given),
+        scale_x V_X[phi] (phi given) or none (ace_apply_h)."""
+        p = _prec(prec)
+        x, nx, ldx = _block(X, p, grid.ng, "X")
+        if out is None:
+            out = torch.empty_like(X, memory_format=torch.contiguous_format)
+        y, ny, ldy = _block(out, p, grid.ng, "Y")
+        vp = None
+        if vloc is not None:
+            want = torch.float64 if p == ACE_FP64 else torch.float32
+            if vloc.dtype != want or not vloc.is_cuda or vloc.numel() != grid.ng or \
+                    not vloc.is_contiguous():
+                raise TypeError(f"vloc must be a contiguous CUDA {want} tensor of N_g values")
+            vp = ctypes.c_void_p(vloc.data_ptr())
+        xp, nxi, ldxi = _block(xi, p, grid.ng, "xi") if xi is not None else (None, 0, 0)
+        pp, nph, ldph = _block(phi, p, grid.ng, "phi") if phi is not None else (None, 0, 0)
+        g = grid.as_c()
+        self._bind_stream()
+        self._check(self._lib.ace_apply_h(self._h, ctypes.byref(g), p, vp, xp, nxi, ldxi, pp, nph,
+                                          ldph, float(scale_x), x, nx, ldx, y, ldy))
+        return out
+
+    def combine(self, grid: Grid, prec, a, A, b=0.0, B=None, c=0.0, C=None, out=None):
+        """D = a A + b B + c C on orbital blocks (ace_combine)."""
+        p = _prec(prec)
+        ap, n, lda = _block(A, p, grid.ng, "A")
+        bp, _, ldb = _block(B, p, grid.ng, "B") if B is not None else (None, 0, 0)
+        cp, _, ldc = _block(C, p, grid.ng, "C") if C is not None else (None, 0, 0)
+        if out is None:
+            out = torch.empty_like(A, memory_format=torch.contiguous_format)
+        dp, _, ldd = _block(out, p, grid.ng, "D")
+        g = grid.as_c()
+        self._bind_stream()
+        self._check(self._lib.ace_combine(self._h, ctypes.byref(g), p, n, float(a), ap, lda,
+                                          float(b), bp, ldb, float(c), cp, ldc, dp, ldd))
+        return out
+
+    def rayleigh_ritz(self, X, HX, grid: Grid, prec, out_X=None, out_HX=None, evals=None):
+        """Ritz pairs of H on span(X) (X orthonormal, HX = H X): returns
+        (X Q, HX Q, eigenvalues ascending as a float64 device tensor)."""
+        p = _prec(prec)
+        x, n, ldx = _block(X, p, grid.ng, "X")
+        h, nh, ldh = _block(HX, p, grid.ng, "HX")
+        if nh != n:
+            raise ValueError("X and HX must hold the same number of orbitals")
+        if out_X is None:
+            out_X = torch.empty_like(X, memory_format=torch.contiguous_format)
+        if out_HX is None:
+            out_HX = torch.empty_like(X, memory_format=torch.contiguous_format)
+        ox, _, ldo = _block(out_X, p, grid.ng, "Xout")
+        oh, _, ldo2 = _block(out_HX, p, grid.ng, "HXout")
+        if ldo2 != ldo:
+            raise ValueError("out_X and out_HX need the same leading dimension")
+        if evals is None:
+            evals = torch.empty(n, dtype=torch.float64, device=X.device)
+        g = grid.as_c()
+        self._bind_stream()
+        self._check(self._lib.ace_rayleigh_ritz(self._h, ctypes.byref(g), p, x, ldx, h, ldh, n, ox,
+                                                oh, ldo, ctypes.c_void_p(evals.data_ptr())))
+        return out_X, out_HX, evals
+
     def build_batched(self, instances, prec, n_branches: int = 4):
         """Build W (and xi when an instance has one) for many independent systems.
 

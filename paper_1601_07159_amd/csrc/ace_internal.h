@@ -17,6 +17,9 @@ struct ace_ctx_s {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_used = 0;
+  // Bytes at the start of the workspace that ws_begin / ws_take skip (a piece
+  // one entry point keeps alive across an inner call that carves its own).
+  size_t ws_prefix = 0;
   // Sub-arena (batched builds): while sub_base is set, ws_begin/ws_take carve
   // from [sub_base, sub_base + sub_bytes) and never reallocate.
   char* sub_base = nullptr;
@@ -122,6 +125,9 @@ struct BuildPlan {
 };
 BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t elem_bytes, int nocc, int nband,
                      bool psi_starts_with_phi);
+// Workspace of ace_apply_h for n_x vectors (exchange from n_xi projection
+// vectors or n_phi orbitals; 0 for none).
+size_t hamiltonian_ws_bytes(ace_ctx c, const GridInfo& g, size_t eb, int nx, int nxi, int nphi);
 // Workspace the compression takes for n_band vectors; alias_eb > 0 adds the
 // copy of xi (n_band x N_g elements of alias_eb bytes) that xi == W needs.
 size_t compress_ws_bytes(int nb, long ng, size_t alias_eb = 0);
@@ -153,12 +159,17 @@ ace_status launch(ace_ctx c, const char* name, void (*kern)(KArgs...), dim3 grid
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 
+// Kernel kind used internally for the kinetic operator -1/2 Laplacian: the
+// pair machinery with one "orbital" of ones and the kernel |G|^2 / 2 gives
+// ifftn(|G|^2/2 fftn(x)) (scale -1).
+constexpr int kKindKinetic = 2;
+
 // Pair FFT stages (fft_passes.hip).
-// W = scale * (*dscale if dscale else 1) * V_X[phi] psi
+// W = scale * (*dscale if dscale else 1) * V_X[phi] psi   (accumulate: W += ...)
 template <typename T>
 ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                         const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale,
-                        const double* dscale = nullptr);
+                        const double* dscale = nullptr, bool accumulate = false);
 template <typename T>
 ace_status energy_direct_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc,
                               long ldphi, double* ex_dev);

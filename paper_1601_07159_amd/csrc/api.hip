@@ -36,13 +36,15 @@ bool stream_capturing(ace_ctx c) {
 }
 
 ace_status ws_begin(ace_ctx c, size_t total) {
-  c->ws_used = 0;
   total = align_up(total ? total : 256, 256);
   if (c->sub_base) {
+    c->ws_used = 0;
     if (total > c->sub_bytes) return fail(c, ACE_E_NOMEM, "internal: batched workspace plan");
     return ACE_OK;
   }
-  if (total <= c->ws_bytes) return ACE_OK;
+  c->ws_used = c->ws_prefix;
+  if (c->ws_prefix + total <= c->ws_bytes) return ACE_OK;
+  if (c->ws_prefix) return fail(c, ACE_E_NOMEM, "internal: workspace plan with a kept prefix");
   // Growing synchronises and allocates, neither of which a stream capture
   // allows: refuse before touching the capture or the current buffer.
   if (stream_capturing(c))
@@ -519,6 +521,10 @@ ACE_EXPORT ace_status ace_reserve(ace_ctx c, const ace_grid* grid, ace_prec prec
   need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, std::max(max_nx, 1), g.ng));
   need = std::max(need, mat + gemm_cn_scratch_bytes(max_nband, max_nocc, g.ng));
   need = std::max(need, energy_direct_ws_bytes(c, g, eb, max_nocc));
+  // ace_apply_h (exchange from xi or from the occupied orbitals) and the
+  // Rayleigh-Ritz step of the eigensolver on up to max(n_band, n_x) vectors
+  need = std::max(need, hamiltonian_ws_bytes(c, g, eb, std::max(max_nx, 1), max_nband, max_nocc));
+  need = std::max(need, 4 * mat + gemm_cn_scratch_bytes(nmax, nmax, g.ng));
   return ws_begin(c, need);
 }
 

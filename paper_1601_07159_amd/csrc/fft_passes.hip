@@ -49,7 +49,9 @@ __global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n,
   const double gx = twopi * m0 / L0, gy = twopi * m1 / L1, gz = twopi * m2 / L2;
   const double g2 = gx * gx + gy * gy + gz * gz;
   double K;
-  if (g2 > 0.0) {
+  if (kind == kKindKinetic) {
+    K = 0.5 * g2;  // -1/2 Laplacian
+  } else if (g2 > 0.0) {
     K = kFourPi / g2;
     if (kind == ACE_ERFC) K *= -expm1(-g2 / (4.0 * mu * mu));
   } else {
@@ -1413,7 +1415,8 @@ ace_status accum(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* buf, cx<T
 template <int N, typename T>
 ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                      const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW, double scale,
-                     const double* dscale) {
+                     const double* dscale, bool accumulate) {
+  const int acc0 = accumulate ? 1 : 0;  // the first contribution to a band adds to W
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
@@ -1435,7 +1438,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
                              (int)all)) != ACE_OK)
       return st;
     if ((st = plane<N, T>(c, buf, Kt, (int)all)) != ACE_OK) return st;
-    return accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nband, 0, 3);
+    return accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nband, acc0, 3);
   }
   if (sym && pl.symblk == 0) {
     // occupied block: the triangle i <= j of pair spectra, every column j < n_occ
@@ -1445,14 +1448,14 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
         ACE_OK)
       return st;
     if ((st = plane<N, T>(c, buf, Kt, (int)tri)) != ACE_OK) return st;
-    if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nocc, 0, 1)) != ACE_OK)
+    if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nocc, acc0, 1)) != ACE_OK)
       return st;
     jstart = nocc;
   } else if (sym) {
     // occupied block in blocks of b: chunk (I, J), I <= J, in a fixed order;
     // a band is written by its first contribution and accumulated afterwards
     const int b = pl.symblk, nblk = (nocc + b - 1) / b;
-    std::vector<char> started(nblk, 0);
+    std::vector<char> started(nblk, (char)acc0);
     for (int J = 0; J < nblk; ++J)
       for (int I = 0; I <= J; ++I) {
         const int i0 = I * b, ni = std::min(b, nocc - i0);
@@ -1495,7 +1498,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
           ACE_OK)
         return st;
       if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
-      if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, Ac, j0, Bc, i0 > 0 ? 1 : 0, 0)) !=
+      if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, Ac, j0, Bc, (i0 > 0 || accumulate) ? 1 : 0, 0)) !=
           ACE_OK)
         return st;
     }
@@ -1591,11 +1594,12 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
 template <typename T>
 ace_status build_W_impl(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, long ldphi,
                         const cx<T>* psi, int nband, long ldpsi, cx<T>* W, long ldW,
-                        double scale, const double* dscale) {
+                        double scale, const double* dscale, bool accumulate) {
   switch (g.n) {
-#define ACE_CASE(NV) \
-  case NV:           \
-    return build_W_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale, dscale);
+#define ACE_CASE(NV)                                                                    \
+  case NV:                                                                              \
+    return build_W_n<NV, T>(c, g, phi, nocc, ldphi, psi, nband, ldpsi, W, ldW, scale, dscale, \
+                            accumulate);
     ACE_FOR_EACH_N(ACE_CASE)
 #undef ACE_CASE
     default:
@@ -1640,10 +1644,10 @@ template ace_status build_W_real_impl<double>(ace_ctx, const GridInfo&, const do
                                               const double*);
 template ace_status build_W_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int, long,
                                         const cx<float>*, int, long, cx<float>*, long, double,
-                                        const double*);
+                                        const double*, bool);
 template ace_status build_W_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int, long,
                                          const cx<double>*, int, long, cx<double>*, long, double,
-                                         const double*);
+                                         const double*, bool);
 template ace_status energy_direct_impl<float>(ace_ctx, const GridInfo&, const cx<float>*, int,
                                               long, double*);
 template ace_status energy_direct_impl<double>(ace_ctx, const GridInfo&, const cx<double>*, int,

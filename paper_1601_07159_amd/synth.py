@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for the ACE build.
 
-This module only manufactures orbitals; it performs none of the exchange
-arithmetic (no pair densities, no Coulomb kernel, no compression).  Both the
+This module only manufactures inputs (orbitals, and a local potential for the
+eigensolver loops); it performs none of the exchange arithmetic (no pair
+densities, no Coulomb kernel, no compression).  Both the
 FP64 oracle tests and the GPU path draw their inputs from here, so that the
 two sides consume byte-identical arrays.
 
@@ -161,3 +162,22 @@ def batched_instances(count: int = 48, seed: int = 1000, orbital_seed: int = 200
 
 def instance_orbitals(inst) -> np.ndarray:
     return smooth_orbitals(inst["n"], inst["L"], inst["nband"], inst["seed"], draw="sphere")
+
+
+def local_potential(n, L, seed: int, depth: float = 1.0, gmax2: float = 3.0) -> np.ndarray:
+    """A smooth random real local potential (stands for V_ion + V_H in the
+    linear eigenvalue problem), float64, shape (n0, n1, n2): Fourier
+    coefficients (a + i b) exp(-|G|^2/2) on |G|^2 <= gmax2 (a, b ~ N(0, 1) from
+    default_rng(seed)), made Hermitian (c(-G) = conj c(G)) so the field is real,
+    G = 0 removed, then scaled so that min V = -depth."""
+    n3 = _as3(n, int)
+    L3 = _as3(L, float)
+    g2 = _g2_grid(n3, L3)
+    rng = np.random.default_rng(seed)
+    c = (rng.standard_normal(n3) + 1j * rng.standard_normal(n3)) * np.exp(-g2 / 2.0)
+    c = c * ((g2 <= gmax2) & (g2 > 0))
+    # Hermitian part: the coefficient at -G (index -k mod n per axis) conjugated
+    cm = np.conj(c[(-np.arange(n3[0])) % n3[0]][:, (-np.arange(n3[1])) % n3[1]]
+                 [:, :, (-np.arange(n3[2])) % n3[2]])
+    v = np.real(np.fft.ifftn(0.5 * (c + cm)))
+    return np.ascontiguousarray(depth * v / (-np.min(v)))
