@@ -46,6 +46,12 @@ WORKLOADS = {
     "cfg5": dict(n=64, L=27.0, nocc=128, nband=128, nx=0, kind="coulomb", mu=0.0, prec="fp32",
                  desc="autograd E_X(phi) forward + hand-written backward, 64^3 grid, "
                       "L=27 bohr, N_occ=128, complex64"),
+    "scf": dict(n=48, L=20.5, nocc=64, nband=80, nx=0, kind="erfc", mu=0.106, prec="fp32",
+                alpha=0.25, extra=8, degree=8, inner=10, outer=12, depth=2.0,
+                desc="Alg. 1 / Alg. 2 loops: H = -1/2 Laplacian + V_loc + 0.25 V_X (erfc, "
+                     "mu=0.106), 48^3 grid, L=20.5 bohr, N_occ=64, Chebyshev-filtered "
+                     "subspace iteration (degree 8, 8 buffer vectors), 10 inner "
+                     "iterations per outer iteration, complex64"),
 }
 
 HBM_PEAK_GBS = 8000.0
@@ -203,6 +209,8 @@ def main():
         return run_batched(args, cfg)
     if args.workload == "cfg5":
         return run_autograd(args, cfg)
+    if args.workload == "scf":
+        return run_scf(args, cfg)
     prec = cfg["prec"]
     n, L, nocc, nband, nx = cfg["n"], cfg["L"], cfg["nocc"], cfg["nband"], cfg["nx"]
     applies = cfg.get("applies", 1)
@@ -645,6 +653,80 @@ def run_autograd(args, cfg):
     if not args.no_cpu:
         out["cpu_baseline"] = with_ratios(cpu_baseline(dict(cfg, nband=nocc)), out["value"])
     print(json.dumps(out), flush=True)
+
+
+def run_scf(args, cfg):
+    """The loops of Alg. 1 (V_X applied by pair solves in every Hamiltonian
+    application) and Alg. 2 (V_ACE), and the loop without exchange, on the
+    same input: time per inner (eigensolver) iteration and per ACE
+    construction (the ratio the paper's timing figure reports), then the
+    exchange-energy differences per outer iteration for the oversampling
+    ratios r = N_band / N_occ = 1, 1.25, 1.5, 2 and for Alg. 1 (the
+    oversampling study).  All loops start from the orbitals of the loop
+    without exchange, converged first (as hybrid calculations start from a
+    semilocal one)."""
+    import numpy as np
+    import torch
+
+    from paper_1601_07159_amd import ace, synth
+    from paper_1601_07159_amd.scf import ScfLoop
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n, L, nocc, prec = cfg["n"], cfg["L"], cfg["nocc"], cfg["prec"]
+    grid = ace.Grid.cubic(n, L, cfg["kind"], cfg["mu"])
+    ctx = ace.Context(0)
+    vloc = synth.local_potential(n, L, seed=11, depth=cfg["depth"])
+    ratios = [1.0, 1.25, 1.5, 2.0]
+    nb_max = int(round(nocc * max(ratios))) + cfg["extra"]
+    log(f"bench: scf: start orbitals ({nb_max}) and the loop without exchange")
+    X0 = torch.from_numpy(synth.smooth_orbitals(n, L, nb_max, seed=0)).to(
+        dev, torch.complex64).reshape(nb_max, -1)
+    base = ScfLoop(ctx, grid, prec, vloc, nocc, nb_max - cfg["extra"], 0.0, "none",
+                   cfg["degree"]).run(X0, n_inner=30, n_outer=1)
+    Xs = base["X"].clone()
+    nband = cfg["nband"]
+    nb = nband + cfg["extra"]
+    timing = {}
+    for mode in ("none", "vx", "ace"):
+        log(f"bench: scf: timing mode {mode}")
+        lp = ScfLoop(ctx, grid, prec, vloc, nocc, nband, cfg["alpha"], mode, cfg["degree"])
+        lp.run(Xs[:nb].clone(), n_inner=2, n_outer=1)           # warm-up
+        lp.times = {"inner": [], "ace_build": [], "apply_h": []}
+        lp.run(Xs[:nb].clone(), n_inner=cfg["inner"], n_outer=args.steps, timing=True)
+        timing[mode] = {"inner_ms": float(np.median(lp.times["inner"])),
+                        "ace_build_ms": float(np.median(lp.times["ace_build"]))}
+    per_outer = {m: timing[m]["inner_ms"] * cfg["inner"] + timing[m]["ace_build_ms"]
+                 for m in timing}
+    conv = {}
+    for r in ratios:
+        nbr = int(round(nocc * r))
+        log(f"bench: scf: convergence r = {r} (N_band = {nbr})")
+        lp = ScfLoop(ctx, grid, prec, vloc, nocc, nbr, cfg["alpha"], "ace", cfg["degree"])
+        out = lp.run(Xs[:nbr + cfg["extra"]].clone(), n_inner=cfg["inner"],
+                     n_outer=cfg["outer"])
+        conv[f"ace_r{r}"] = out["E_X"]
+    log("bench: scf: convergence without ACE (Alg. 1)")
+    lp = ScfLoop(ctx, grid, prec, vloc, nocc, nband, cfg["alpha"], "vx", cfg["degree"])
+    out = lp.run(Xs[:nb].clone(), n_inner=cfg["inner"], n_outer=cfg["outer"])
+    conv["vx"] = out["E_X"]
+    diffs = {k: [abs(v[i] - v[i - 1]) for i in range(1, len(v))] for k, v in conv.items()}
+    ratio = per_outer["vx"] / per_outer["ace"]
+    roofline = {"bound": "hbm", "kernel": "n/a (loop timing)", "achieved": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    extra = {"time_per_inner_iteration_ms": {m: round(timing[m]["inner_ms"], 3) for m in timing},
+             "ace_construction_ms": round(timing["ace"]["ace_build_ms"], 3),
+             "time_per_outer_iteration_ms": {m: round(v, 2) for m, v in per_outer.items()},
+             "outer_time_ratio_vx_over_ace": ratio,
+             "outer_time_ratio_vx_over_none": per_outer["vx"] / per_outer["none"],
+             "outer_time_ratio_ace_over_none": per_outer["ace"] / per_outer["none"],
+             "E_X_per_outer": conv, "E_X_difference_per_outer": diffs,
+             "n_band_timing": nband, "buffer_vectors": cfg["extra"]}
+    config = {"workload": f"scf: {cfg['desc']}", "precision": prec, "grid": n, "L_bohr": L,
+              "n_occ": nocc, "parallelism": "single GPU"}
+    out = _base_record(args, cfg, "outer-iteration time ratio, Alg. 1 (V_X) / Alg. 2 (ACE)",
+                       ratio, "x", per_outer["ace"], "f32", config, roofline, extra)
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":
