@@ -422,9 +422,12 @@ def main():
         extra["errors_vs_oracle"] = golden_errors(ctx, cfg, grid, prec, bufs, Xs, nocc)
 
     if args.copy_probe:
-        src = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device=dev)
+        # a plain copy kernel of known size (256 MiB read, 256 MiB written) for
+        # the HBM counter scaling; torch's copy_ may go through a DMA engine,
+        # which the counters do not see, so the copy is an elementwise kernel
+        src = torch.zeros(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         extra["copy_probe_bytes"] = 2 * src.numel() * 8
 
