@@ -533,8 +533,10 @@ def _base_record(args, cfg, metric, value, unit, ms, dtype, config, roofline, ex
 
 
 def run_batched(args, cfg):
-    """48 independent instances; one step = ace_build_batched (W and xi of every
-    instance) replayed from its HIP graph."""
+    """48 independent instances; one step = ace_build_W_batched (W and xi of
+    every instance) replayed from its HIP graph.  Beside it (extra.forms), the
+    same 48 builds as plain single calls on one stream, FP32 and FP64 (unless
+    --no-fp64)."""
     import concurrent.futures as cf
 
     import torch
@@ -571,15 +573,38 @@ def run_batched(args, cfg):
             r = ctx.autotune(ace.Grid.cubic(n, med["L"]), "fp32", med["nocc"], med["nband"])
             tuned[n] = {k: r[k] for k in ("pair_budget", "jblock", "fft_shape", "accum_shape")}
             log(f"bench: cfg4: autotuned n={n}: {tuned[n]} ({r['ms']:.2f} ms per build)")
-    ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32", n_branches=nbr),
-                     args.steps, args.warmup) * 1e3
+    ctx.set_tuning("branches", nbr)
+    ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32"), args.steps, args.warmup) * 1e3
     bad = [k for k, d in enumerate(insts) if int(d["info"].item()) != 0]
+    log(f"bench: cfg4: batched graph {ms:.2f} ms per step")
+
+    def singles(ds, prec):
+        for d in ds:
+            ctx.build_W(d["phi"], d["psi"], d["grid"], prec, out=d["W"])
+            ctx.compress(d["psi"], d["W"], d["grid"], prec, out=d["xi"], info=d["info"])
+
+    forms = {"batched_graph_fp32_ms": round(ms, 3)}
+    steps_f = max(1, min(args.steps, 3))
+    forms["single_calls_fp32_ms"] = round(
+        _timed_loop(lambda: singles(insts, "fp32"), steps_f, 1) * 1e3, 3)
+    log(f"bench: cfg4: single calls fp32 {forms['single_calls_fp32_ms']:.2f} ms per step")
+    if not args.no_fp64:
+        d64 = []
+        for d in insts:
+            x = d["psi"].to(torch.complex128)
+            d64.append(dict(grid=d["grid"], phi=x[:d["phi"].shape[0]], psi=x,
+                            W=torch.empty_like(x), xi=torch.empty_like(x), info=d["info"]))
+        forms["single_calls_fp64_ms"] = round(
+            _timed_loop(lambda: singles(d64, "fp64"), steps_f, 1) * 1e3, 3)
+        log(f"bench: cfg4: single calls fp64 {forms['single_calls_fp64_ms']:.2f} ms per step")
+        del d64
+        torch.cuda.empty_cache()
     achieved = fft_bytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "all FFT passes of the batch (graph replay)",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": fft_bytes, "avg_launch_ms": round(ms, 4)}
-    extra = {"instances": len(insts), "branches": nbr, "autotuned": tuned,
+    extra = {"instances": len(insts), "branches": nbr, "autotuned": tuned, "forms": forms,
              "pairs_per_step": pairs,
              "transformed_pairs_per_step": transformed, "failed_cholesky": bad,
              "fft_roofline_ms": fft_bytes / (HBM_PEAK_GBS * 1e9) * 1e3}

@@ -26,7 +26,7 @@
  *         potentials apart as real and imaginary parts).  Small matrices
  *         (L_out) stay complex128 with zero imaginary parts.  Not available
  *         for real orbitals: the direct energy form (xi == NULL), the batched
- *         build and the tuner (ACE_E_UNSUPPORTED).
+ *         build, the tuner and the eigensolver pieces (ACE_E_UNSUPPORTED).
  * Inner product.  <f, g> = dV * sum_r conj(f(r)) g(r); orbitals are expected
  *         to satisfy <phi_i, phi_j> = delta_ij where the paper says so.
  * Ownership.  The caller owns every pointer passed in; the library never frees
@@ -271,17 +271,20 @@ ace_status ace_rayleigh_ritz(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  * Batched build (Section 3 for many independent systems): for every instance,
  * W = scale * V_X[phi] psi as ace_build_W, then (when xi != NULL) the
  * compression of ace_compress with L not returned and the pivot status in
- * *info_dev (required then).  Instances may differ in grid, cell, kernel and
- * sizes; all share the precision.  They are spread over n_branches (1..16)
- * concurrent streams, each with its own workspace slice, and the whole batch
- * is captured into one HIP graph that is launched on the context stream.  A
- * later call with an identical instance array (same pointers, sizes and
- * settings) replays that graph without re-enqueueing; the data behind the
- * pointers may change between calls.  Pointers must not overlap across
- * instances' outputs.  Never synchronises.
+ * *info_dev (required then).  Instances may differ in grid, cell, kernel,
+ * sizes and complex precision (ACE_FP64, ACE_FP32 or ACE_MIXED each).  They
+ * are spread over concurrent branch streams (the tuning knob
+ * ACE_TUNE_BRANCHES, 1..16, default 4), each with its own workspace slice, and
+ * the whole batch is captured into one HIP graph that is launched on the
+ * context stream.  A later call with an identical instance array (same
+ * pointers, sizes and settings) replays that graph without re-enqueueing; the
+ * data behind the pointers may change between calls.  Pointers must not
+ * overlap across instances' outputs; xi may not alias W here.  Never
+ * synchronises.
  */
 typedef struct {
   ace_grid grid;
+  int prec;               /* ace_prec of this instance (complex precisions) */
   const void* phi; int n_occ; long ld_phi;
   const void* psi; int n_band; long ld_psi;
   void* W; long ld_W;
@@ -289,8 +292,7 @@ typedef struct {
   int* info_dev;          /* device int, required when xi != NULL */
   double scale;
 } ace_instance;
-ace_status ace_build_batched(ace_ctx ctx, ace_prec prec, int n_inst, const ace_instance* inst,
-                             int n_branches);
+ace_status ace_build_W_batched(ace_ctx ctx, int n_inst, const ace_instance* inst);
 
 /*
  * Autotuner of the build for one grid size and precision: times ace_build_W on
@@ -345,9 +347,11 @@ ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
  *  ACE_TUNE_ACCUM_SHAPE  accumulate pass: 1 one thread per pencil (accumulator
  *                        in LDS), 16 a pencil split over four lanes 16 apart
  *                        (accumulator in registers), 0 (default) automatic
+ *  ACE_TUNE_BRANCHES     concurrent branch streams of ace_build_W_batched
+ *                        (1..16; 0 restores the default 4)
  * They change speed only; results agree to rounding. */
 enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2,
-       ACE_TUNE_FFT_SHAPE = 3, ACE_TUNE_ACCUM_SHAPE = 4 };
+       ACE_TUNE_FFT_SHAPE = 3, ACE_TUNE_ACCUM_SHAPE = 4, ACE_TUNE_BRANCHES = 5 };
 ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
 ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
 

@@ -15,13 +15,13 @@ ACE_COULOMB, ACE_ERFC = 0, 1
 EXPORTED = [
     "ace_create", "ace_destroy", "ace_set_stream", "ace_reserve", "ace_build_W", "ace_compress",
     "ace_apply", "ace_apply_noalloc", "ace_exchange_energy", "ace_exchange_energy_grad", "ace_orthonormalize",
-    "ace_supported_n", "ace_build_batched", "ace_autotune", "ace_tune_load",
+    "ace_supported_n", "ace_build_W_batched", "ace_autotune", "ace_tune_load",
     "ace_profile_enable", "ace_profile_reset", "ace_profile_count", "ace_profile_get",
     "ace_set_pair_budget", "ace_set_tuning", "ace_get_tuning", "ace_status_string",
     "ace_last_error", "ace_apply_h", "ace_combine", "ace_rayleigh_ritz",
 ]
 (ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE,
- ACE_TUNE_ACCUM_SHAPE) = 0, 1, 2, 3, 4
+ ACE_TUNE_ACCUM_SHAPE, ACE_TUNE_BRANCHES) = 0, 1, 2, 3, 4, 5
 
 
 class AceGrid(ctypes.Structure):
@@ -30,7 +30,7 @@ class AceGrid(ctypes.Structure):
 
 
 class AceInstance(ctypes.Structure):
-    _fields_ = [("grid", AceGrid),
+    _fields_ = [("grid", AceGrid), ("prec", ctypes.c_int),
                 ("phi", ctypes.c_void_p), ("n_occ", ctypes.c_int), ("ld_phi", ctypes.c_long),
                 ("psi", ctypes.c_void_p), ("n_band", ctypes.c_int), ("ld_psi", ctypes.c_long),
                 ("W", ctypes.c_void_p), ("ld_W", ctypes.c_long),
@@ -57,7 +57,7 @@ _PROTOS = {
     "ace_exchange_energy_grad": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _vp, _l]),
     "ace_orthonormalize": (_i, [_vp, _gp, _i, _vp, _i, _l, _vp, _l, _vp]),
     "ace_supported_n": (_i, [ctypes.POINTER(_i), _i]),
-    "ace_build_batched": (_i, [_vp, _i, _i, ctypes.POINTER(AceInstance), _i]),
+    "ace_build_W_batched": (_i, [_vp, _i, ctypes.POINTER(AceInstance)]),
     "ace_autotune": (_i, [_vp, _gp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_l),
                           ctypes.POINTER(_l), ctypes.POINTER(_i), ctypes.POINTER(_i),
                           ctypes.POINTER(_d)]),

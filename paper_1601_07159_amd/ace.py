@@ -25,7 +25,7 @@ PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED, "real64": ACE_RE
         "real32": ACE_REAL32}
 _TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
               "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE,
-              "accum_shape": _lib.ACE_TUNE_ACCUM_SHAPE}
+              "accum_shape": _lib.ACE_TUNE_ACCUM_SHAPE, "branches": _lib.ACE_TUNE_BRANCHES}
 
 
 class AceError(RuntimeError):
@@ -330,17 +330,22 @@ class Context:
                                                 oh, ldo, ctypes.c_void_p(evals.data_ptr())))
         return out_X, out_HX, evals
 
-    def build_batched(self, instances, prec, n_branches: int = 4):
-        """Build W (and xi when an instance has one) for many independent systems.
+    def build_batched(self, instances, prec, n_branches: int = None):
+        """Build W (and xi when an instance has one) for many independent systems
+        (ace_build_W_batched).
 
         ``instances``: list of dicts with keys grid (Grid), phi, psi, W, and
-        optionally xi, info (CUDA int32, required with xi) and scale.  The
-        first call captures a HIP graph; identical later calls replay it."""
-        p = _prec(prec)
+        optionally xi, info (CUDA int32, required with xi), scale and prec
+        (default: ``prec``).  n_branches (optional) sets the tuning knob of
+        the branch streams.  The first call captures a HIP graph; identical
+        later calls replay it."""
+        if n_branches is not None:
+            self.set_tuning("branches", int(n_branches))
         arr = (_lib.AceInstance * len(instances))()
         self._keep = []
         for k, d in enumerate(instances):
             g = d["grid"]
+            p = _prec(d.get("prec", prec))
             a, na, lda = _block(d["phi"], p, g.ng, "phi")
             b, nb, ldb = _block(d["psi"], p, g.ng, "psi")
             w, nw, ldw = _block(d["W"], p, g.ng, "W")
@@ -348,6 +353,7 @@ class Context:
                 raise ValueError("W must hold n_band orbitals")
             e = arr[k]
             e.grid = g.as_c()
+            e.prec = p
             e.phi, e.n_occ, e.ld_phi = a, na, lda
             e.psi, e.n_band, e.ld_psi = b, nb, ldb
             e.W, e.ld_W = w, ldw
@@ -363,7 +369,7 @@ class Context:
                 e.xi, e.ld_xi, e.info_dev = None, 0, None
             e.scale = float(d.get("scale", 1.0))
         self._bind_stream()
-        self._check(self._lib.ace_build_batched(self._h, p, len(instances), arr, int(n_branches)))
+        self._check(self._lib.ace_build_W_batched(self._h, len(instances), arr))
 
     def autotune(self, grid: Grid, prec, n_occ: int, n_band: int, cache_path=None) -> dict:
         """Time the build over pair budgets, band blocks and FFT line shapes; keep

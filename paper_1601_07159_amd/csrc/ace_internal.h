@@ -49,6 +49,7 @@ struct ace_ctx_s {
   bool use_symmetry = true;  // i <-> j pair symmetry on the occupied block
   int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread, 4 quad, 8 octet, 16 split
   int accum_shape = 0;       // accumulate pass: 0 auto, 1 thread per pencil, 16 split lines
+  int branches = 4;          // branch streams of the batched build
   int num_cus = 256;
   std::string last_error;
   std::string tune_cache;              // default cache file of ace_autotune ("" = none)

@@ -473,6 +473,10 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
         return fail(c, ACE_E_ARG, "accumulate shape 0, 1 or 16");
       c->accum_shape = (int)value;
       return ACE_OK;
+    case ACE_TUNE_BRANCHES:
+      if (value > 16) return fail(c, ACE_E_ARG, "branches 1..16 (0 = default)");
+      c->branches = value ? (int)value : 4;
+      return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }
@@ -485,6 +489,7 @@ ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
     case ACE_TUNE_SYMMETRY: *value = c->use_symmetry ? 1 : 0; return ACE_OK;
     case ACE_TUNE_FFT_SHAPE: *value = c->fft_shape; return ACE_OK;
     case ACE_TUNE_ACCUM_SHAPE: *value = c->accum_shape; return ACE_OK;
+    case ACE_TUNE_BRANCHES: *value = c->branches; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }

@@ -53,13 +53,11 @@ ace_status enqueue_instance(ace_ctx c, const ace_instance& in, const GridInfo& g
   return ACE_OK;
 }
 
-std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_instance* inst,
-                                    int nbr) {
+std::vector<unsigned char> make_key(ace_ctx c, int n, const ace_instance* inst, int nbr) {
   std::vector<unsigned char> k(sizeof(ace_instance) * n + 72);
   std::memcpy(k.data(), inst, sizeof(ace_instance) * n);
   unsigned char* t = k.data() + sizeof(ace_instance) * n;
   const void* ws = c->ws;
-  std::memcpy(t, &prec, sizeof prec);
   std::memcpy(t + 8, &nbr, sizeof nbr);
   std::memcpy(t + 16, &ws, sizeof ws);
   std::memcpy(t + 24, &c->ws_bytes, sizeof c->ws_bytes);
@@ -78,17 +76,18 @@ std::vector<unsigned char> make_key(ace_ctx c, ace_prec prec, int n, const ace_i
 
 using namespace ace;
 
-ACE_EXPORT ace_status ace_build_batched(ace_ctx c, ace_prec prec, int n_inst,
-                                        const ace_instance* inst, int n_branches) {
+ACE_EXPORT ace_status ace_build_W_batched(ace_ctx c, int n_inst, const ace_instance* inst) {
   if (!c) return ACE_E_ARG;
   if (n_inst < 1 || !inst) return fail(c, ACE_E_ARG, "no instances");
-  if (n_branches < 1 || n_branches > 16) return fail(c, ACE_E_ARG, "n_branches must be 1..16");
-  if (prec == ACE_REAL32 || prec == ACE_REAL64)
-    return fail(c, ACE_E_UNSUPPORTED, "batched builds take complex orbitals");
-  const size_t eb = elem_bytes(prec);
+  const int n_branches = c->branches;
   std::vector<Planned> plan(n_inst);
   for (int k = 0; k < n_inst; ++k) {
     const ace_instance& in = inst[k];
+    const ace_prec prec = (ace_prec)in.prec;
+    if (prec != ACE_FP64 && prec != ACE_FP32 && prec != ACE_MIXED)
+      return fail(c, prec == ACE_REAL32 || prec == ACE_REAL64 ? ACE_E_UNSUPPORTED : ACE_E_ARG,
+                  "batched builds take complex precisions (ACE_FP64, ACE_FP32, ACE_MIXED)");
+    const size_t eb = elem_bytes(prec);
     ACE_TRY(check_grid(c, &in.grid, prec, &plan[k].g));
     const GridInfo& g = plan[k].g;
     ACE_TRY(check_block(c, in.phi, in.n_occ, in.ld_phi, g, "instance phi"));
@@ -134,7 +133,7 @@ ACE_EXPORT ace_status ace_build_batched(ace_ctx c, ace_prec prec, int n_inst,
   ACE_TRY(ws_begin(c, total));  // grows the workspace before any capture
   ACE_TRY(ensure_branches(c, nbr));
 
-  std::vector<unsigned char> key = make_key(c, prec, n_inst, inst, nbr);
+  std::vector<unsigned char> key = make_key(c, n_inst, inst, nbr);
   if (c->graph_exec && key == c->graph_key) {
     hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);  // replay
     return e == hipSuccess ? ACE_OK : hip_fail(c, e, "hipGraphLaunch");
@@ -168,6 +167,7 @@ ACE_EXPORT ace_status ace_build_batched(ace_ctx c, ace_prec prec, int n_inst,
     c->sub_bytes = bbytes[b];
     for (int k = 0; k < n_inst && st == ACE_OK; ++k) {
       if (plan[k].branch != b) continue;
+      const ace_prec prec = (ace_prec)inst[k].prec;
       st = prec == ACE_FP64 ? enqueue_instance<double>(c, inst[k], plan[k].g, kNative)
                             : enqueue_instance<float>(c, inst[k], plan[k].g, compress_mode(prec));
     }

@@ -1,4 +1,4 @@
-"""GPU parity of ace_build_batched (many independent ACE builds in one HIP
+"""GPU parity of ace_build_W_batched (many independent ACE builds in one HIP
 graph) against the FP64 oracle and against the single-instance entry points."""
 import concurrent.futures as cf
 
@@ -58,6 +58,51 @@ def test_batched_fp64_matches_oracle_and_single_calls(ace):
         W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], "fp64")
         xi1 = ctx.compress(d["psi"], W1, d["grid"], "fp64")
         assert torch.equal(W1, d["W"]) and torch.equal(xi1, d["xi"])
+    ctx.close()
+
+
+def test_batched_mixed_precisions_in_one_batch(ace):
+    # each instance names its own precision; FP64 and FP32 instances share one
+    # graph and each equals its single call in that precision, bit for bit
+    import torch
+    insts, host = [], []
+    for k, prec in enumerate(["fp64", "fp32", "fp64", "fp32"]):
+        i, h = _make(ace, prec, [SMALL[k]], 90 + k)
+        i[0]["prec"] = prec
+        insts += i
+        host += h
+    ctx = ace.Context()
+    ctx.build_batched(insts, "fp32", n_branches=2)
+    torch.cuda.synchronize()
+    for d, (psi, og, nocc) in zip(insts, host):
+        assert int(d["info"].item()) == 0
+        assert d["W"].dtype == (torch.complex128 if d["prec"] == "fp64" else torch.complex64)
+        W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], d["prec"])
+        xi1 = ctx.compress(d["psi"], W1, d["grid"], d["prec"])
+        torch.cuda.synchronize()
+        assert torch.equal(W1, d["W"]) and torch.equal(xi1, d["xi"])
+        ref = O.build_W(psi[:nocc], psi, og)
+        assert rel(to_np(d["W"]), ref) <= (1e-10 if d["prec"] == "fp64" else 1e-5)
+    ctx.close()
+
+
+def test_batched_branch_knob(ace):
+    # the branch count is a tuning knob (1..16, 0 = default); the result does
+    # not depend on it
+    import torch
+    insts, _ = _make(ace, "fp32", SMALL[:5], 120)
+    ctx = ace.Context()
+    outs = []
+    for nbr in (1, 5, 16):
+        ctx.set_tuning("branches", nbr)
+        assert ctx.get_tuning("branches") == nbr
+        ctx.build_batched(insts, "fp32")
+        torch.cuda.synchronize()
+        outs.append([d["W"].clone() for d in insts])
+    for a, b in zip(outs[0], outs[2]):
+        assert torch.equal(a, b)
+    with pytest.raises(ace.AceError):
+        ctx.set_tuning("branches", 17)
     ctx.close()
 
 
