@@ -186,6 +186,8 @@ def main():
                     help="line shape of the slab and plane passes (0 = library default)")
     ap.add_argument("--accum-shape", type=int, default=0, choices=[0, 1, 16],
                     help="form of the accumulate pass (0 = library default)")
+    ap.add_argument("--batch-form", type=int, default=0, choices=[0, 1, 2],
+                    help="cfg4: W stage of the batched build (1 launches, 2 persistent)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="cfg4: skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -574,6 +576,20 @@ def run_batched(args, cfg):
             tuned[n] = {k: r[k] for k in ("pair_budget", "jblock", "fft_shape", "accum_shape")}
             log(f"bench: cfg4: autotuned n={n}: {tuned[n]} ({r['ms']:.2f} ms per build)")
     ctx.set_tuning("branches", nbr)
+    forms = {}
+    if args.batch_form == 0:
+        # both forms of the W stage, the library default timed last
+        ctx.set_tuning("batch_form", 2)
+        forms["batched_persistent_fp32_ms"] = round(
+            _timed_loop(lambda: ctx.build_batched(insts, "fp32"), args.steps, args.warmup) * 1e3, 3)
+        log(f"bench: cfg4: persistent form {forms['batched_persistent_fp32_ms']:.2f} ms per step")
+        ctx.set_tuning("batch_form", 1)
+        forms["batched_launches_fp32_ms"] = round(
+            _timed_loop(lambda: ctx.build_batched(insts, "fp32"), args.steps, args.warmup) * 1e3, 3)
+        log(f"bench: cfg4: launches form {forms['batched_launches_fp32_ms']:.2f} ms per step")
+        ctx.set_tuning("batch_form", 0)
+    else:
+        ctx.set_tuning("batch_form", args.batch_form)
     ms = _timed_loop(lambda: ctx.build_batched(insts, "fp32"), args.steps, args.warmup) * 1e3
     bad = [k for k, d in enumerate(insts) if int(d["info"].item()) != 0]
     log(f"bench: cfg4: batched graph {ms:.2f} ms per step")
@@ -583,7 +599,7 @@ def run_batched(args, cfg):
             ctx.build_W(d["phi"], d["psi"], d["grid"], prec, out=d["W"])
             ctx.compress(d["psi"], d["W"], d["grid"], prec, out=d["xi"], info=d["info"])
 
-    forms = {"batched_graph_fp32_ms": round(ms, 3)}
+    forms["batched_graph_fp32_ms"] = round(ms, 3)
     steps_f = max(1, min(args.steps, 3))
     forms["single_calls_fp32_ms"] = round(
         _timed_loop(lambda: singles(insts, "fp32"), steps_f, 1) * 1e3, 3)

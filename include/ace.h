@@ -272,11 +272,22 @@ ace_status ace_rayleigh_ritz(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  * W = scale * V_X[phi] psi as ace_build_W, then (when xi != NULL) the
  * compression of ace_compress with L not returned and the pivot status in
  * *info_dev (required then).  Instances may differ in grid, cell, kernel,
- * sizes and complex precision (ACE_FP64, ACE_FP32 or ACE_MIXED each).  They
- * are spread over concurrent branch streams (the tuning knob
- * ACE_TUNE_BRANCHES, 1..16, default 4), each with its own workspace slice, and
- * the whole batch is captured into one HIP graph that is launched on the
- * context stream.  A later call with an identical instance array (same
+ * sizes and complex precision (ACE_FP64, ACE_FP32 or ACE_MIXED each).  Two
+ * forms of the W stage (tuning knob ACE_TUNE_BATCH_FORM):
+ *   1 (launches): each instance's pass kernels run on one of several
+ *     concurrent branch streams (ACE_TUNE_BRANCHES, 1..16, default 4), each
+ *     with its own workspace slice;
+ *   2 (persistent): one persistent kernel per (grid size, precision) runs the
+ *     passes of all instances of that size as tasks from a device queue with
+ *     dependency counters, on the co-resident workgroups; it uses the
+ *     one-thread-per-line slab and plane passes (ACE_TUNE_FFT_SHAPE 1 gives
+ *     single calls with the same arithmetic) and caps each instance's pair
+ *     budget so that one size's buffers stay within min(24 GiB, a quarter of
+ *     the free device memory).  A wait that exceeds 10 s (a defect) ends the
+ *     kernel and leaves NaN in W, which the compression reports as a failed
+ *     factorisation.
+ * The compressions run on the branch streams.  The whole batch is captured
+ * into one HIP graph that is launched on the context stream.  A later call with an identical instance array (same
  * pointers, sizes and settings) replays that graph without re-enqueueing; the
  * data behind the pointers may change between calls.  Pointers must not
  * overlap across instances' outputs; xi may not alias W here.  Never
@@ -349,9 +360,12 @@ ace_status ace_set_pair_budget(ace_ctx ctx, long bytes);
  *                        (accumulator in registers), 0 (default) automatic
  *  ACE_TUNE_BRANCHES     concurrent branch streams of ace_build_W_batched
  *                        (1..16; 0 restores the default 4)
+ *  ACE_TUNE_BATCH_FORM   W stage of ace_build_W_batched: 1 launches on branch
+ *                        streams, 2 persistent kernels, 0 (default) form 1
  * They change speed only; results agree to rounding. */
 enum { ACE_TUNE_PAIR_BUDGET = 0, ACE_TUNE_JBLOCK = 1, ACE_TUNE_SYMMETRY = 2,
-       ACE_TUNE_FFT_SHAPE = 3, ACE_TUNE_ACCUM_SHAPE = 4, ACE_TUNE_BRANCHES = 5 };
+       ACE_TUNE_FFT_SHAPE = 3, ACE_TUNE_ACCUM_SHAPE = 4, ACE_TUNE_BRANCHES = 5,
+       ACE_TUNE_BATCH_FORM = 6 };
 ace_status ace_set_tuning(ace_ctx ctx, int key, long value);
 ace_status ace_get_tuning(ace_ctx ctx, int key, long* value);
 

@@ -21,7 +21,7 @@ EXPORTED = [
     "ace_last_error", "ace_apply_h", "ace_combine", "ace_rayleigh_ritz",
 ]
 (ACE_TUNE_PAIR_BUDGET, ACE_TUNE_JBLOCK, ACE_TUNE_SYMMETRY, ACE_TUNE_FFT_SHAPE,
- ACE_TUNE_ACCUM_SHAPE, ACE_TUNE_BRANCHES) = 0, 1, 2, 3, 4, 5
+ ACE_TUNE_ACCUM_SHAPE, ACE_TUNE_BRANCHES, ACE_TUNE_BATCH_FORM) = 0, 1, 2, 3, 4, 5, 6
 
 
 class AceGrid(ctypes.Structure):

@@ -25,7 +25,8 @@ PREC = {"fp64": ACE_FP64, "fp32": ACE_FP32, "mixed": ACE_MIXED, "real64": ACE_RE
         "real32": ACE_REAL32}
 _TUNE_KEYS = {"pair_budget": _lib.ACE_TUNE_PAIR_BUDGET, "jblock": _lib.ACE_TUNE_JBLOCK,
               "symmetry": _lib.ACE_TUNE_SYMMETRY, "fft_shape": _lib.ACE_TUNE_FFT_SHAPE,
-              "accum_shape": _lib.ACE_TUNE_ACCUM_SHAPE, "branches": _lib.ACE_TUNE_BRANCHES}
+              "accum_shape": _lib.ACE_TUNE_ACCUM_SHAPE, "branches": _lib.ACE_TUNE_BRANCHES,
+              "batch_form": _lib.ACE_TUNE_BATCH_FORM}
 
 
 class AceError(RuntimeError):

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libace.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 SOURCES = ["api.hip", "fft_passes.hip", "dense.hip", "gemm_mfma.hip", "batched.hip",
-           "tune.hip", "noalloc.hip", "eigen.hip"]
+           "tune.hip", "noalloc.hip", "eigen.hip", "persist.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -11,6 +11,33 @@
 #include "../../include/ace.h"
 #include "fft_core.h"
 
+// One pass launch of a build, recorded for the persistent batched kernel
+// (plain data, copied to device memory).
+struct ace_plaunch {
+  int kind;  // ace::PassKind
+  int mode, i0, A, j0, nbc, accumulate, npairs;
+  long p0;
+  long units;  // logical units of the launch (grid points, slabs, planes, pencil tiles)
+  const void* phi;
+  const void* psi;
+  void* buf;
+  void* W;
+  void* Kt;
+  long ldphi, ldpsi, ldW;
+  int n, table_kind;
+  double L0, L1, L2, mu, g0, coef;
+};
+
+// One task of the persistent kernel: units [u0, u1) of launch `launch`, run
+// once every task of launch `wait` (-1: none) has finished (wait_count tasks).
+struct ace_ptask {
+  int launch;
+  int wait;
+  int wait_count;
+  int pad;
+  long u0, u1;
+};
+
 struct ace_ctx_s {
   hipStream_t stream = nullptr;
   int device = 0;
@@ -50,6 +77,13 @@ struct ace_ctx_s {
   int fft_shape = 0;         // slab/plane line shape: 0 auto, 1 thread, 4 quad, 8 octet, 16 split
   int accum_shape = 0;       // accumulate pass: 0 auto, 1 thread per pencil, 16 split lines
   int branches = 4;          // branch streams of the batched build
+  int batch_form = 0;        // batched build: 0 default, 1 per-instance launches, 2 persistent
+  // Batched build, persistent form: while `record` is set, the pass launchers
+  // of build_W_impl append descriptors there instead of launching, and
+  // plan_build caps the pair budget at budget_cap (0 = no cap).
+  std::vector<struct ace_plaunch>* record = nullptr;
+  size_t budget_cap = 0;
+  std::vector<void*> graph_bufs;  // device buffers the cached graph reads
   int num_cus = 256;
   std::string last_error;
   std::string tune_cache;              // default cache file of ace_autotune ("" = none)
@@ -159,6 +193,22 @@ ace_status launch(ace_ctx c, const char* name, void (*kern)(KArgs...), dim3 grid
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
+// Pass kinds of a recorded launch.
+enum PassKind { kPassTable = 0, kPassSlab = 1, kPassPlane = 2, kPassAccum = 3, kPassAccumQ = 4 };
+
+// Persistent batched kernel (persist.hip) for grid size n and element bytes eb
+// (8: complex64, 16: complex128): threads per workgroup, units per step of a
+// pass kind, and the co-resident workgroups per CU.
+int persist_threads(int n, size_t eb);
+int persist_step(int n, size_t eb, int kind);
+ace_status persist_blocks_per_cu(ace_ctx c, int n, size_t eb, bool accq, int* out);
+// Enqueues (on c->stream) the reset of ctl/done, the persistent kernel over
+// ntasks tasks on `grid` workgroups, and the poisoning of every accumulated W
+// (NaN in its first element) if a wait timed out.
+ace_status persist_run(ace_ctx c, int n, size_t eb, bool accq, const ace_plaunch* L, int nlaunch,
+                       const ace_ptask* tasks, int ntasks, int* ctl, int* done, int grid,
+                       long long spin_ticks);
 
 // Kernel kind used internally for the kinetic operator -1/2 Laplacian: the
 // pair machinery with one "orbital" of ones and the kernel |G|^2 / 2 gives

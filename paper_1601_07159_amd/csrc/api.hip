@@ -413,10 +413,9 @@ ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
   }
   if (c->fork_event) hipEventDestroy(c->fork_event);
   if (c->stream_event) hipEventDestroy(c->stream_event);
-  if (c->ws) {
-    hipStreamSynchronize(c->stream);
-    hipFree(c->ws);
-  }
+  if (c->ws || !c->graph_bufs.empty()) hipStreamSynchronize(c->stream);
+  if (c->ws) hipFree(c->ws);
+  for (void* p : c->graph_bufs) hipFree(p);
   for (auto& p : c->pending) {
     hipEventDestroy(p.e0);
     hipEventDestroy(p.e1);
@@ -477,6 +476,10 @@ ACE_EXPORT ace_status ace_set_tuning(ace_ctx c, int key, long value) {
       if (value > 16) return fail(c, ACE_E_ARG, "branches 1..16 (0 = default)");
       c->branches = value ? (int)value : 4;
       return ACE_OK;
+    case ACE_TUNE_BATCH_FORM:
+      if (value > 2) return fail(c, ACE_E_ARG, "batch form 0, 1 or 2");
+      c->batch_form = (int)value;
+      return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }
@@ -490,6 +493,7 @@ ACE_EXPORT ace_status ace_get_tuning(ace_ctx c, int key, long* value) {
     case ACE_TUNE_FFT_SHAPE: *value = c->fft_shape; return ACE_OK;
     case ACE_TUNE_ACCUM_SHAPE: *value = c->accum_shape; return ACE_OK;
     case ACE_TUNE_BRANCHES: *value = c->branches; return ACE_OK;
+    case ACE_TUNE_BATCH_FORM: *value = c->batch_form; return ACE_OK;
     default: return fail(c, ACE_E_ARG, "unknown tuning key");
   }
 }

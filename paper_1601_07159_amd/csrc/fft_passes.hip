@@ -23,140 +23,20 @@
 #include <vector>
 
 #include "ace_internal.h"
+#include "pass_bodies.h"
 
 namespace ace {
 
 namespace {
-
-constexpr double kFourPi = 12.566370614359172954;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n, double L0,
                                                       double L1, double L2, int kind, double mu,
                                                       double g0, double coef,
                                                       const double* __restrict__ dscale) {
-  const long ng = (long)n * n * n;
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= ng) return;
-  const int k2 = (int)(idx % n);
-  const int k1 = (int)((idx / n) % n);
-  const int k0 = (int)(idx / ((long)n * n));
-  // integer frequency of FFT bin k (the Nyquist bin's sign does not matter: squared)
-  const int m0 = k0 <= n / 2 ? k0 : k0 - n;
-  const int m1 = k1 <= n / 2 ? k1 : k1 - n;
-  const int m2 = k2 <= n / 2 ? k2 : k2 - n;
-  const double twopi = 6.283185307179586477;
-  const double gx = twopi * m0 / L0, gy = twopi * m1 / L1, gz = twopi * m2 / L2;
-  const double g2 = gx * gx + gy * gy + gz * gz;
-  double K;
-  if (kind == kKindKinetic) {
-    K = 0.5 * g2;  // -1/2 Laplacian
-  } else if (g2 > 0.0) {
-    K = kFourPi / g2;
-    if (kind == ACE_ERFC) K *= -expm1(-g2 / (4.0 * mu * mu));
-  } else {
-    K = g0;
-  }
-  // dscale (nullable): a further factor read from device memory (the upstream
-  // gradient of the energy in the backward pass), so no host round trip
-  Kt[idx] = T(coef * (dscale ? *dscale : 1.0) * K);
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
-// physical workgroup b runs on XCD b % 8.  The launches pad the grid to a
-// multiple of 8 and map physical ids so that XCD x receives the contiguous
-// logical range [x G/8, (x+1) G/8); logical ids >= count exit at once.  Logical
-// order is chosen so that neighbours share inputs (the same x0 slab of phi and
-// psi, the same pencil tile of phi), which then stay in one L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ long xcd_logical(long bid, long padded) {
-  return (bid % kXcds) * (padded / kXcds) + bid / kXcds;
-}
-inline unsigned xcd_pad(long count) { return (unsigned)((count + kXcds - 1) / kXcds * kXcds); }
-
-
-// Streaming (non-temporal) store of one complex value.  The forward slab
-// pass writes every pair spectrum once and re-reads the orbital slabs from
-// L2; plain stores of the 2-3 GB stream evict those slabs (measured at
-// 48^3: 0.88 -> 0.68 ms for the pass with streaming stores).
-template <typename T>
-__device__ __forceinline__ void store_nt(cx<T>* p, cx<T> v) {
-  if constexpr (sizeof(T) == 4) {
-    typedef float f2 __attribute__((ext_vector_type(2)));
-    __builtin_nontemporal_store(f2{v.x, v.y}, reinterpret_cast<f2*>(p));
-  } else {
-    typedef double d2 __attribute__((ext_vector_type(2)));
-    __builtin_nontemporal_store(d2{v.x, v.y}, reinterpret_cast<d2*>(p));
-  }
-}
-
-// Units of the packed real triangle before column c: sum over c' < c of
-// (floor(c'/2) + 1).
-__host__ __device__ __forceinline__ long real_tri_units(int c) {
-  const long q = c / 2;
-  return c + ((c & 1) ? q * q : q * (q - 1));
-}
-// Column c and row pair m of triangle unit p (p < real_tri_units(n)).
-__device__ __forceinline__ void real_tri_of(long p, int* c, int* m) {
-  int cc = (int)(2.0 * sqrt((double)p));  // close to the root of c^2/4 + c/2 = p
-  while (cc > 0 && real_tri_units(cc) > p) --cc;
-  while (real_tri_units(cc + 1) <= p) ++cc;
-  *c = cc;
-  *m = (int)(p - real_tri_units(cc));
-}
-
-// Pair of block-local index p.
-//  mode 0: rectangle, i = i0 + p % A, j = j0 + p / A
-//  mode 1: upper triangle i <= j of a diagonal block starting at i0 (= j0),
-//          block triangle index p0 + p (row-major in j)
-//  mode 3: the whole occupied triangle (A = n_occ orbitals, A(A+1)/2 pairs)
-//          followed by the rectangle of orbitals x bands j0 = A ... in one chunk
-__device__ __forceinline__ void pair_of(int mode, int i0, int A, int j0, long p0, long p, int* i,
-                                        int* j) {
-  if (mode == 3) {
-    const long tri = (long)A * (A + 1) / 2;
-    if (p >= tri) {
-      *i = (int)((p - tri) % A);
-      *j = j0 + (int)((p - tri) / A);
-      return;
-    }
-    mode = 1;  // triangle of the occupied block, which starts at orbital i0
-    j0 = i0;
-  }
-  if (mode == 0) {
-    *i = i0 + (int)(p % A);
-    *j = j0 + (int)(p / A);
-  } else {
-    const long g = p0 + p;
-    long jj = (long)((sqrt(8.0 * (double)g + 1.0) - 1.0) * 0.5);
-    while (jj * (jj + 1) / 2 > g) --jj;
-    while ((jj + 1) * (jj + 2) / 2 <= g) ++jj;
-    *j = j0 + (int)jj;
-    *i = i0 + (int)(g - jj * (jj + 1) / 2);
-  }
-}
-
-// One-thread-per-line variants of the slab and plane passes: each thread owns
-// a whole row or column in registers.  A workgroup takes P slabs (planes) of
-// N lines each, P chosen so that P N fills whole waves within an LDS budget
-// (N = 48 planes: four in three full waves instead of one wave of 48 lanes).
-// The slab pass gets the smaller budget: it issues two loads per value and
-// measured slower at N = 48 with four slabs (fewer workgroups per CU).
-template <int N, typename T>
-constexpr int t1_group(long lds_budget) {
-  int best = 1;
-  double best_use = 0.0;
-  for (int P = 1; P <= 16; ++P) {
-    const long lds = (long)P * N * (N + 1) * (long)sizeof(cx<T>);
-    if (P * N > 1024 || lds > lds_budget) break;
-    const int waves = (P * N + 63) / 64;
-    const double use = (double)(P * N) / (64.0 * waves);
-    if (use > best_use + 1e-9) {
-      best_use = use;
-      best = P;
-    }
-  }
-  return best;
+  if (idx >= (long)n * n * n) return;
+  kernel_table_at<T>(Kt, idx, n, L0, L1, L2, kind, mu, g0, coef, dscale);
 }
 
 // Forward slab pass: one group of N threads per (x0, pair).
@@ -165,106 +45,23 @@ __global__ __launch_bounds__(N * P) void k_pair_fwd_slab_t1(const cx<T>* __restr
                                                          const cx<T>* __restrict__ psi, long ldpsi,
                                                          cx<T>* __restrict__ buf, int mode, int i0,
                                                          int A, int j0, long p0, int npairs) {
-  constexpr int NN = N * N;
-  constexpr int LD = N + 1;
-  __shared__ cx<T> s_all[P * N * LD];
+  __shared__ cx<T> s_all[P * N * (N + 1)];
   const long total = (long)N * npairs;
   const long lid0 = xcd_logical(blockIdx.x, gridDim.x) * P;
   if (lid0 >= total) return;  // the whole workgroup
-  // group q of the workgroup (compile-time 0 when P = 1, keeping the LDS
-  // addresses constant offsets)
-  const int q = P == 1 ? 0 : (int)threadIdx.x / N;
-  const int t = P == 1 ? (int)threadIdx.x : (int)threadIdx.x - q * N;
-  cx<T>* s = s_all + q * N * LD;
-  // a group past the end (only in the last workgroup) redoes the last unit
-  // and does not store
-  const bool live = P == 1 || lid0 + q < total;
-  const long lid = live ? lid0 + q : total - 1;
-  const int x0 = (int)(lid / npairs);
-  const int p = (int)(lid - (long)x0 * npairs);
-  int i, j;
-  pair_of(mode, i0, A, j0, p0, p, &i, &j);
-  const cx<T>* a = phi + (size_t)i * ldphi + (size_t)x0 * NN;
-  const cx<T>* b = psi + (size_t)j * ldpsi + (size_t)x0 * NN;
-  {
-    // issue every load of the slab before the first use
-    cx<T> va[N], vb[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) va[r] = a[r * N + t];
-#pragma unroll
-    for (int r = 0; r < N; ++r) vb[r] = b[r * N + t];
-#pragma unroll
-    for (int r = 0; r < N; ++r) s[r * LD + t] = cmulc(va[r], vb[r]);
-  }
-  __syncthreads();
-  cx<T> v[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = s[t * LD + k];
-  fft_line<N, -1, T>(v);
-#pragma unroll
-  for (int k = 0; k < N; ++k) s[t * LD + k] = v[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = s[k * LD + t];
-  fft_line<N, -1, T>(v);
-  if (!live) return;
-  cx<T>* out = buf + (size_t)p * N * NN + (size_t)x0 * NN;
-#pragma unroll
-  for (int k = 0; k < N; ++k) store_nt(&out[k * N + t], v[k]);
+  slab_t1_body<N, T, P>(s_all, (int)threadIdx.x, false, lid0, total, phi, ldphi, psi, ldpsi, buf,
+                        mode, i0, A, j0, p0, npairs);
 }
 
-// Plane pass: one group of N threads per (k1 plane, pair).  The plane
-// buf[k0][k1][.] (N rows of N contiguous values, rows N^2 apart) goes through
-// LDS: forward FFT along axis 0, multiply by K', inverse FFT along axis 0, then
-// inverse FFT along axis 2.  Loads and stores are contiguous N-wide rows.
+// Plane pass: one group of N threads per (k1 plane, pair).
 template <int N, typename T, int P>
 __global__ __launch_bounds__(N * P) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
                                                         const T* __restrict__ Kt, int npairs) {
-  constexpr int NN = N * N;
-  constexpr int LD = N + 1;
-  __shared__ cx<T> s_all[P * N * LD];
+  __shared__ cx<T> s_all[P * N * (N + 1)];
   const long total = (long)N * npairs;
   const long lid0 = xcd_logical(blockIdx.x, gridDim.x) * P;
   if (lid0 >= total) return;  // the whole workgroup
-  // group q of the workgroup (compile-time 0 when P = 1, keeping the LDS
-  // addresses constant offsets)
-  const int q = P == 1 ? 0 : (int)threadIdx.x / N;
-  const int t = P == 1 ? (int)threadIdx.x : (int)threadIdx.x - q * N;
-  cx<T>* s = s_all + q * N * LD;
-  // a group past the end (only in the last workgroup) redoes the last unit
-  // and does not store
-  const bool live = P == 1 || lid0 + q < total;
-  const long lid = live ? lid0 + q : total - 1;
-  const int k1 = (int)(lid / npairs);
-  const int p = (int)(lid - (long)k1 * npairs);
-  cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
-  cx<T> v[N];
-  // axis 0 (column t of the plane, k2 = t): forward, kernel, inverse.  The
-  // column is read straight from global memory (lanes on consecutive k2).
-#pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = plane[(size_t)r * NN + t];
-  fft_line<N, -1, T>(v);
-  const T* kcol = Kt + (size_t)k1 * N + t;
-#pragma unroll
-  for (int r = 0; r < N; ++r) {
-    const T kk = kcol[(size_t)r * NN];
-    v[r].x *= kk;
-    v[r].y *= kk;
-  }
-  fft_line<N, +1, T>(v);
-#pragma unroll
-  for (int r = 0; r < N; ++r) s[r * LD + t] = v[r];
-  __syncthreads();
-  // axis 2 (row t of the plane, x0 = t): inverse
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = s[t * LD + k];
-  fft_line<N, +1, T>(v);
-#pragma unroll
-  for (int k = 0; k < N; ++k) s[t * LD + k] = v[k];
-  __syncthreads();
-  if (!live) return;
-#pragma unroll
-  for (int r = 0; r < N; ++r) plane[(size_t)r * NN + t] = s[r * LD + t];
+  plane_t1_body<N, T, P>(s_all, (int)threadIdx.x, false, lid0, total, buf, Kt, npairs);
 }
 
 // The slab and plane passes split every line FFT over the 4 lanes of a quad
@@ -642,200 +439,34 @@ __global__ __launch_bounds__(8 * N) void k_plane_kernel_oct(cx<T>* __restrict__ 
   for (int q = 0; q < M; ++q) plane[(size_t)(8 * q + rr) * NN + cc] = s[(8 * q + rr) * LD + cc];
 }
 
-// Pencil pass with accumulation: one thread per (x0, x2) pencil along axis 1,
-// 64 pencils per workgroup, one band per workgroup row of the grid.  Loops
-// over the orbitals i of the block: inverse FFT along axis 1, multiply by
-// phi_i, accumulate into a thread-private LDS column; the band is written once
-// per block.  Lanes hold consecutive pencils, so every global access is a
-// contiguous row; no barrier is needed anywhere.
-// Band j = j0 + b, orbital i = i0 + a; the spectrum of the pair comes from
-//  mode 0: a rectangle chunk (i0 + a, j0 + b) at index a + A b;
-//  mode 1: the triangle chunk of a diagonal block (i0 = j0): pairs i <= j at
-//          local index j'(j'+1)/2 + i', and u_ij = conj(u_ji) for i > j;
-//  mode 2: a rectangle chunk stored the other way round, (j, i) at index
-//          b + nbc a, read conjugated (u_ij = conj(u_ji));
-//  mode 3: the single chunk of pair_of's mode 3 (i0 = j0 = 0, A = n_occ):
-//          bands j < A as mode 1, bands j >= A from the rectangle after the
-//          triangle.
+// Accumulate pass, one thread per pencil (accum_lds_body), one wave per
+// logical workgroup.
 template <int N, typename T>
 __global__ __launch_bounds__(64) void k_pencil_accum(const cx<T>* __restrict__ phi, long ldphi,
                                                      const cx<T>* __restrict__ buf,
                                                      cx<T>* __restrict__ W, long ldW, int i0,
                                                      int A, int j0, int nbc, int accumulate,
                                                      int mode) {
-  constexpr int NN = N * N;
-  constexpr int TILES = (NN + 63) / 64;
+  constexpr int TILES = (N * N + 63) / 64;
   __shared__ cx<T> acc[N * 64];
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
   if (lid >= (long)TILES * nbc) return;
-  const int tile = (int)(lid / nbc);
-  const int b = (int)(lid - (long)tile * nbc);
-  const int t = threadIdx.x;
-  const int q = tile * 64 + t;
-  if (q >= NN) return;
-  const int x0 = q / N, x2 = q - x0 * N;
-  const size_t off = (size_t)x0 * NN + x2;
-  // Branch-free body: the accumulator starts at zero, and all loads of an
-  // iteration (the pencil of u_ij and of phi_i) are issued before any use.
-#pragma unroll
-  for (int k = 0; k < N; ++k) acc[k * 64 + t] = cx<T>{T(0), T(0)};
-  const int j = j0 + b;
-  // Bands of a triangle block take their orbitals in round-robin tournament
-  // order (the circle method over the block's A bands, a bye when A is odd):
-  // at step s band b meets partner p(s, b), and p(s, p(s, b)) = b, so the two
-  // waves that need the spectrum of the pair {b, p} (one as u, one as conj u)
-  // read it at the same step, and the second read finds it in cache.
-  const bool tri = mode == 1 || (mode == 3 && b < A);
-  const int rounds = A - 1 + (A & 1);  // players A (+1 bye when odd), fixed player m
-  for (int s = 0; s < A; ++s) {
-    int a = s;
-    if (tri) {
-      const int m = rounds;
-      if (s >= rounds) {
-        a = b;  // even A: the band's own pair last
-      } else if (b == m) {
-        a = s;
-      } else {
-        int q = (2 * s - b) % m;
-        q = q < 0 ? q + m : q;
-        a = q == b ? m : q;
-        if (a == A) a = b;  // odd A: the bye is the band's own pair
-      }
-    }
-    const int i = i0 + a;
-    size_t pidx;
-    bool conj_u;
-    if (mode == 0) {
-      pidx = (size_t)a + (size_t)A * b;
-      conj_u = false;
-    } else if (mode == 1 || (mode == 3 && b < A)) {
-      const int il = a, jl = b;  // local indices in the diagonal block
-      pidx = il <= jl ? (size_t)jl * (jl + 1) / 2 + il : (size_t)il * (il + 1) / 2 + jl;
-      conj_u = il > jl;
-    } else if (mode == 3) {
-      pidx = (size_t)A * (A + 1) / 2 + (size_t)a + (size_t)A * (b - A);
-      conj_u = false;
-    } else {
-      pidx = (size_t)b + (size_t)nbc * a;
-      conj_u = true;
-    }
-    const cx<T>* src = buf + pidx * N * NN + off;
-    const cx<T>* fp = phi + (size_t)i * ldphi + off;
-    cx<T> v[N];
-    cx<T> f[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = src[k * N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) f[k] = fp[k * N];
-    fft_line<N, +1, T>(v);
-    if (conj_u) {
-#pragma unroll
-      for (int k = 0; k < N; ++k) v[k].y = -v[k].y;
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) acc[k * 64 + t] = cadd(acc[k * 64 + t], cmul(f[k], v[k]));
-  }
-  cx<T>* w = W + (size_t)j * ldW + off;
-  if (accumulate) {
-    cx<T> old[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) old[k] = w[k * N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) w[k * N] = cadd(old[k], acc[k * 64 + t]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < N; ++k) w[k * N] = acc[k * 64 + t];
-  }
+  accum_lds_body<N, T>(acc, (int)threadIdx.x, lid, phi, ldphi, buf, W, ldW, i0, A, j0, nbc,
+                       accumulate, mode);
 }
 
-// Index of the orbital that band b of a triangle block (A bands) meets at step
-// s: the round-robin tournament of k_pencil_accum (circle method, a bye when A
-// is odd, the band's own pair at the bye or, for even A, at the last step).
-__device__ __forceinline__ int tri_partner(int A, int b, int s) {
-  const int m = A - 1 + (A & 1);
-  if (s >= m) return b;
-  if (b == m) return s;
-  int q = (2 * s - b) % m;
-  q = q < 0 ? q + m : q;
-  const int a = q == b ? m : q;
-  return a == A ? b : a;
-}
-
-// Accumulate pass on split lines: every (x0, x2) pencil along axis 1 is split
-// over 4 lanes 16 apart (lane p + 16 h holds part h of pencil p: it loads rows
-// h + 4 m and, after fft_quad_d2b, holds rows k + M kp(h)), 16 consecutive
-// pencils per one-wave workgroup, so every load and store of 16 lanes is one
-// contiguous row segment; one band per workgroup row of the grid.  The band's
-// accumulator stays in registers (no LDS), so occupancy is set by registers
-// alone.  Modes, pair indices and the tournament order of the triangle bands
-// as in k_pencil_accum.
+// Accumulate pass on split lines (accum_q_body), one wave per logical
+// workgroup.
 template <int N, typename T>
 __global__ __launch_bounds__(64) void k_pencil_accum_q(const cx<T>* __restrict__ phi, long ldphi,
                                                        const cx<T>* __restrict__ buf,
                                                        cx<T>* __restrict__ W, long ldW, int i0,
                                                        int A, int j0, int nbc, int accumulate,
                                                        int mode) {
-  constexpr int NN = N * N;
-  constexpr int M = N / 4;
-  constexpr int TILES = NN / 16;  // N is a multiple of 4
-  static_assert(N % 4 == 0, "quad lines need N divisible by 4");
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
-  if (lid >= (long)TILES * nbc) return;
-  const int tile = (int)(lid / nbc);
-  const int b = (int)(lid - (long)tile * nbc);
-  const int h = (int)threadIdx.x >> 4;
-  const int q = tile * 16 + ((int)threadIdx.x & 15);
-  const int x0 = q / N, x2 = q - x0 * N;
-  const size_t off = (size_t)x0 * NN + x2;
-  cx<T> acc[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) acc[k] = cx<T>{T(0), T(0)};
-  const int j = j0 + b;
-  const bool tri = mode == 1 || (mode == 3 && b < A);
-  for (int s = 0; s < A; ++s) {
-    const int a = tri ? tri_partner(A, b, s) : s;
-    const int i = i0 + a;
-    size_t pidx;
-    bool conj_u;
-    if (mode == 0) {
-      pidx = (size_t)a + (size_t)A * b;
-      conj_u = false;
-    } else if (tri) {
-      pidx = a <= b ? (size_t)b * (b + 1) / 2 + a : (size_t)a * (a + 1) / 2 + b;
-      conj_u = a > b;
-    } else if (mode == 3) {
-      pidx = (size_t)A * (A + 1) / 2 + (size_t)a + (size_t)A * (b - A);
-      conj_u = false;
-    } else {
-      pidx = (size_t)b + (size_t)nbc * a;
-      conj_u = true;
-    }
-    const cx<T>* src = buf + pidx * N * NN + off;
-    const cx<T>* fp = phi + (size_t)i * ldphi + off;
-    cx<T> v[M], f[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) v[m] = src[(size_t)(h + 4 * m) * N];
-#pragma unroll
-    for (int k = 0; k < M; ++k) f[k] = fp[(size_t)quad_block_index(k, M, h) * N];
-    fft_quad_d2b<N, +1, T, 16>(v, h);
-    const T sg = conj_u ? T(-1) : T(1);
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const cx<T> u = {v[k].x, sg * v[k].y};
-      acc[k] = cadd(acc[k], cmul(f[k], u));
-    }
-  }
-  cx<T>* w = W + (size_t)j * ldW + off;
-  if (accumulate) {
-    cx<T> old[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) old[k] = w[(size_t)quad_block_index(k, M, h) * N];
-#pragma unroll
-    for (int k = 0; k < M; ++k) w[(size_t)quad_block_index(k, M, h) * N] = cadd(old[k], acc[k]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < M; ++k) w[(size_t)quad_block_index(k, M, h) * N] = acc[k];
-  }
+  if (lid >= (long)(N * N / 16) * nbc) return;
+  accum_q_body<N, T>((int)threadIdx.x, lid, phi, ldphi, buf, W, ldW, i0, A, j0, nbc, accumulate,
+                     mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -1210,6 +841,7 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
       if (!jblock) jblock = t.jblock;
     }
   if (!budget) budget = default_pair_budget();
+  if (c->budget_cap && budget > c->budget_cap) budget = c->budget_cap;
   long maxpairs = (long)(budget / pair_bytes);
   if (maxpairs < 1) maxpairs = 1;
   // Band block B (all bands unless tuned otherwise): the accumulating pass runs
@@ -1308,6 +940,23 @@ namespace {
 template <typename T>
 ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
                              const double* dscale = nullptr) {
+  if (c->record) {
+    if (dscale) return fail(c, ACE_E_UNSUPPORTED, "recorded build with a device scale");
+    ace_plaunch l{};
+    l.kind = kPassTable;
+    l.units = g.ng;
+    l.Kt = Kt;
+    l.n = g.n;
+    l.table_kind = g.kind;
+    l.L0 = g.L[0];
+    l.L1 = g.L[1];
+    l.L2 = g.L[2];
+    l.mu = g.mu;
+    l.g0 = g.g0;
+    l.coef = coef;
+    c->record->push_back(l);
+    return ACE_OK;
+  }
   const unsigned blocks = (unsigned)((g.ng + 255) / 256);
   return launch(c, "kernel_table", k_kernel_table<T>, dim3(blocks), dim3(256), 0, Kt, g.n, g.L[0],
                 g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
@@ -1352,6 +1001,25 @@ int pass_form(ace_ctx c, bool plane_pass) {
 template <int N, typename T>
 ace_status fwd_slab(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* psi, long ldpsi,
                     cx<T>* buf, int mode, int i0, int A, int j0, long p0, int np) {
+  if (c->record) {
+    // the persistent kernel runs the one-thread-per-line form
+    ace_plaunch l{};
+    l.kind = kPassSlab;
+    l.units = (long)N * np;
+    l.phi = phi;
+    l.ldphi = ldphi;
+    l.psi = psi;
+    l.ldpsi = ldpsi;
+    l.buf = buf;
+    l.mode = mode;
+    l.i0 = i0;
+    l.A = A;
+    l.j0 = j0;
+    l.p0 = p0;
+    l.npairs = np;
+    c->record->push_back(l);
+    return ACE_OK;
+  }
   const dim3 grid(xcd_pad((long)N * np));
   const int form = pass_form<N, T>(c, false);
   if constexpr (kOctOk<N, T>)
@@ -1372,6 +1040,16 @@ ace_status fwd_slab(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* psi, l
 
 template <int N, typename T>
 ace_status plane(ace_ctx c, cx<T>* buf, const T* Kt, int np) {
+  if (c->record) {
+    ace_plaunch l{};
+    l.kind = kPassPlane;
+    l.units = (long)N * np;
+    l.buf = buf;
+    l.Kt = (void*)Kt;
+    l.npairs = np;
+    c->record->push_back(l);
+    return ACE_OK;
+  }
   const dim3 grid(xcd_pad((long)N * np));
   const int form = pass_form<N, T>(c, true);
   if constexpr (kOctOk<N, T>)
@@ -1406,6 +1084,25 @@ int accum_form(ace_ctx c) {
 template <int N, typename T>
 ace_status accum(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* buf, cx<T>* W, long ldW,
                  int i0, int A, int j0, int nbc, int accumulate, int mode) {
+  if (c->record) {
+    const bool q = accum_form<N, T>(c) != 1;
+    ace_plaunch l{};
+    l.kind = q ? kPassAccumQ : kPassAccum;
+    l.units = (q ? (long)(N * N / 16) : (long)((N * N + 63) / 64)) * nbc;
+    l.phi = phi;
+    l.ldphi = ldphi;
+    l.buf = (void*)buf;
+    l.W = W;
+    l.ldW = ldW;
+    l.i0 = i0;
+    l.A = A;
+    l.j0 = j0;
+    l.nbc = nbc;
+    l.accumulate = accumulate;
+    l.mode = mode;
+    c->record->push_back(l);
+    return ACE_OK;
+  }
   if (accum_form<N, T>(c) == 1) {
     constexpr int TILES = (N * N + 63) / 64;
     return launch(c, "pencil_accum", k_pencil_accum<N, T>, dim3(xcd_pad((long)TILES * nbc)),

@@ -189,3 +189,105 @@ def test_batched_recaptures_after_tuning(ace, tmp_path):
         assert rel(to_np(old), ref) <= 1e-5
     assert changed > 0  # the new setting rounds differently, so a stale graph would show
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Persistent form (ACE_TUNE_BATCH_FORM = 2): one persistent kernel per grid
+# size runs every instance's passes from a task queue.  Its slab and plane
+# passes are the one-thread-per-line forms, so single calls with line shape 1
+# have the same arithmetic and must agree bit for bit.
+
+def _persistent_ctx(ace, budget=0):
+    ctx = ace.Context()
+    ctx.set_tuning("batch_form", 2)
+    ctx.set_tuning("fft_shape", 1)
+    if budget:
+        ctx.set_tuning("pair_budget", budget)
+    return ctx
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_persistent_equals_single_calls(ace, prec):
+    import torch
+    print(f"persistent batch prec={prec}", flush=True)
+    insts, host = _make(ace, prec, SMALL, 200)
+    ctx = _persistent_ctx(ace)
+    ctx.build_batched(insts, prec)
+    torch.cuda.synchronize()
+    t = 1e-10 if prec == "fp64" else 1e-5
+    for d, (psi, og, nocc) in zip(insts, host):
+        assert int(d["info"].item()) == 0
+        W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], prec)
+        xi1 = ctx.compress(d["psi"], W1, d["grid"], prec)
+        torch.cuda.synchronize()
+        assert torch.equal(W1, d["W"]) and torch.equal(xi1, d["xi"])
+        assert rel(to_np(d["W"]), O.build_W(psi[:nocc], psi, og)) <= t
+    ctx.close()
+
+
+def test_persistent_chunked_builds_and_mixed_sizes(ace):
+    # a small pair budget splits every build into chunks (triangle blocks,
+    # rectangles, several accumulations into the same bands), so the tasks of
+    # one instance form a long dependency chain; instances of one size share
+    # one persistent kernel, FP64 and FP32 instances of a size run in two
+    import torch
+    specs = SMALL + [(24, 8.0, 12, 6, "coulomb", 0.0), (16, 6.5, 10, 2, "erfc", 0.3)]
+    insts, host = [], []
+    for k, sp in enumerate(specs):
+        prec = "fp64" if k % 3 == 0 else "fp32"
+        i, h = _make(ace, prec, [sp], 300 + k)
+        i[0]["prec"] = prec
+        insts += i
+        host += h
+    budget = 6 * 32 ** 3 * 16  # a few pairs per chunk at every size
+    ctx = _persistent_ctx(ace, budget)
+    ctx.build_batched(insts, "fp32")
+    torch.cuda.synchronize()
+    for d, (psi, og, nocc) in zip(insts, host):
+        assert int(d["info"].item()) == 0
+        W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], d["prec"])
+        xi1 = ctx.compress(d["psi"], W1, d["grid"], d["prec"])
+        torch.cuda.synchronize()
+        assert torch.equal(W1, d["W"]) and torch.equal(xi1, d["xi"])
+        ref = O.build_W(psi[:nocc], psi, og)
+        assert rel(to_np(d["W"]), ref) <= (1e-10 if d["prec"] == "fp64" else 1e-5)
+    ctx.close()
+
+
+def test_persistent_replay_follows_new_data(ace):
+    import torch
+    insts, _ = _make(ace, "fp32", SMALL[:4], 400)
+    ctx = _persistent_ctx(ace, 4 * 24 ** 3 * 8)
+    ctx.build_batched(insts, "fp32")
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k, d in enumerate(insts):
+            n, L, nocc, extra = SMALL[k][:4]
+            new = synth.smooth_orbitals(n, L, nocc + extra, seed=450 + 10 * rep + k)
+            d["psi"].copy_(to_gpu(new, "fp32"))
+        torch.cuda.synchronize()
+        ctx.build_batched(insts, "fp32")  # replay
+        torch.cuda.synchronize()
+        for d in insts:
+            W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], "fp32")
+            xi1 = ctx.compress(d["psi"], W1, d["grid"], "fp32")
+            torch.cuda.synchronize()
+            assert torch.equal(W1, d["W"]) and torch.equal(xi1, d["xi"])
+    ctx.close()
+
+
+def test_persistent_accumulate_forms(ace):
+    # both accumulate forms (one thread per pencil with LDS accumulators, split
+    # lines with register accumulators) inside the persistent kernel
+    import torch
+    for accum in (1, 16):
+        insts, _ = _make(ace, "fp32", SMALL[:3], 500 + accum)
+        ctx = _persistent_ctx(ace)
+        ctx.set_tuning("accum_shape", accum)
+        ctx.build_batched(insts, "fp32")
+        torch.cuda.synchronize()
+        for d in insts:
+            W1 = ctx.build_W(d["phi"], d["psi"], d["grid"], "fp32")
+            torch.cuda.synchronize()
+            assert torch.equal(W1, d["W"])
+        ctx.close()
