@@ -26,6 +26,8 @@ namespace {
 //             finished blocks of X kept (conjugate-transposed) in C.
 // lda >= n; T is scratch of kCholNB x n.
 constexpr int kCholNB = 16;
+// Loads in flight per thread in the inverse's block-row products.
+constexpr int kInvBatch = 8;
 // Up to this n the current panel (n x kCholNB) is staged in LDS.
 constexpr int kCholPanelRows = 512;
 __shared__ cx<double> chol_panel[kCholNB][kCholPanelRows];
@@ -56,13 +58,28 @@ __device__ __forceinline__ cx<double> quad_bcast(cx<double> v) {
   return {quad_bcast<J>(v.x), quad_bcast<J>(v.y)};
 }
 
+// 1/sqrt(d) from the hardware estimate, refined by three Newton-Raphson steps
+// y <- y (3/2 - d y^2 / 2).
+__device__ __forceinline__ double rsq_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
 __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, int n, double s,
                                               cx<double>* A, int lda, cx<double>* T,
                                               cx<double>* __restrict__ Lout,
                                               cx<double>* __restrict__ C, int* __restrict__ info,
-                                              const int* __restrict__ prior, int real_only) {
+                                              const int* __restrict__ prior, int real_only,
+                                              int do_inverse) {
   constexpr int NB = kCholNB;
   __shared__ int failed;
+  __shared__ double pinv[kCholNB];  // 1 / L_kk of the current diagonal block
   const int t = threadIdx.x, nt = blockDim.x;
   const int lane = t & 63, wave = t >> 6, nw = nt >> 6;
   if (prior && *prior != 0) {
@@ -99,49 +116,50 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
             if (lane == 0) failed = kb + k + 1;
             break;  // uniform across the wave
           }
-          const double r = sqrt(d), inv = 1.0 / r;
+          // 1/sqrt(d) and sqrt(d) from the refined reciprocal square root
+          // (no divide on the serial path)
+          const double inv = rsq_refined(d), r = d * inv;
           wave_sync();
-          if (lane == 0) P[k][k] = {r, 0.0};
+          if (lane == 0) {
+            P[k][k] = {r, 0.0};
+            pinv[k] = inv;
+          }
           const int i = k + 1 + lane;
           if (i < nb) {
             const cx<double> v = P[k][i];
             P[k][i] = {v.x * inv, v.y * inv};
           }
           wave_sync();
-          const int m = nb - k - 1;
-          for (int e = lane; e < m * m; e += 64) {
-            const int ii = k + 1 + e % m, jj = k + 1 + e / m;
-            if (ii < jj) continue;
-            const cx<double> u = cmulcj_d(P[k][ii], P[k][jj]);
-            const cx<double> v = P[jj][ii];
-            P[jj][ii] = {v.x - u.x, v.y - u.y};
+          // rank-1 update of the block's trailing triangle: lane -> (row
+          // offset lane % 16, column offset lane / 16 + 4 t), no divisions
+#pragma unroll
+          for (int tq = 0; tq < 4; ++tq) {
+            const int ii = k + 1 + (lane & 15), jj = k + 1 + (lane >> 4) + 4 * tq;
+            if (ii < nb && jj < nb && ii >= jj) {
+              const cx<double> u = cmulcj_d(P[k][ii], P[k][jj]);
+              const cx<double> v = P[jj][ii];
+              P[jj][ii] = {v.x - u.x, v.y - u.y};
+            }
           }
           wave_sync();
         }
       }
       __syncthreads();
       if (failed) break;
-      // rows below the diagonal block: x L_kk^H = a, one thread per row
+      // rows below the diagonal block: x L_kk^H = a, one thread per row,
+      // solved in place in the LDS panel (a register array indexed by the
+      // loop counters went to scratch memory)
       for (int r = nb + t; r < R; r += nt) {
-        cx<double> x[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) x[c] = c < nb ? P[c][r] : cx<double>{0, 0};
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          if (c >= nb) break;
-          cx<double> v = x[c];
-#pragma unroll
+        for (int c = 0; c < nb; ++c) {
+          cx<double> v = P[c][r];
           for (int d = 0; d < c; ++d) {
-            const cx<double> u = cmulcj_d(x[d], P[d][c]);
+            const cx<double> u = cmulcj_d(P[d][r], P[d][c]);
             v.x -= u.x;
             v.y -= u.y;
           }
-          const double inv = 1.0 / P[c][c].x;
-          x[c] = {v.x * inv, v.y * inv};
+          const double inv = pinv[c];
+          P[c][r] = {v.x * inv, v.y * inv};
         }
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c < nb) P[c][r] = x[c];
       }
       __syncthreads();
       // the finished panel back to A; the trailing lower triangle from the
@@ -154,30 +172,47 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
       // the four (the P[c][j] are wave-uniform broadcasts).  Loads are
       // unconditional from clamped columns; entries above the diagonal or past
       // n are computed on scratch values and not stored.
-      for (int jb = kb + nb + 4 * wave; jb < n; jb += 4 * nw)
-        for (int i = jb + lane; i < n; i += 64) {
-          cx<double> acc[4];
-          int jq[4];
+      // Two row blocks (i and i + 64) per step with all eight loads issued
+      // first, so that a thread waits for memory once per step.
+      for (int jb = kb + nb + 4 * wave; jb < n; jb += 4 * nw) {
+        int jq[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            jq[q] = jb + q < n ? jb + q : n - 1;
-            acc[q] = A[i + (size_t)jq[q] * lda];
+        for (int q = 0; q < 4; ++q) jq[q] = jb + q < n ? jb + q : n - 1;
+        for (int i0 = jb + lane; i0 < n; i0 += 128) {
+          int im[2];
+          cx<double> acc[2][4];
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            im[m] = i0 + 64 * m < n ? i0 + 64 * m : n - 1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[m][q] = A[im[m] + (size_t)jq[q] * lda];
           }
 #pragma unroll
           for (int c = 0; c < NB; ++c) {
             if (c >= nb) break;
-            const cx<double> pi = P[c][i - kb];
+            cx<double> pj[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const cx<double> u = cmulcj_d(pi, P[c][jq[q] - kb]);
-              acc[q].x -= u.x;
-              acc[q].y -= u.y;
+            for (int q = 0; q < 4; ++q) pj[q] = P[c][jq[q] - kb];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+              const cx<double> pi = P[c][im[m] - kb];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const cx<double> u = cmulcj_d(pi, pj[q]);
+                acc[m][q].x -= u.x;
+                acc[m][q].y -= u.y;
+              }
             }
           }
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (jb + q < n && i >= jb + q) A[i + (size_t)(jb + q) * lda] = acc[q];
+          for (int m = 0; m < 2; ++m) {
+            const int i = i0 + 64 * m;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (i < n && jb + q < n && i >= jb + q) A[i + (size_t)(jb + q) * lda] = acc[m][q];
+          }
         }
+      }
       __syncthreads();
       continue;
     }
@@ -256,6 +291,7 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
       for (int i = lane; i < n; i += 64)
         Lout[i + (size_t)j * n] = (i >= j) ? A[i + (size_t)j * lda] : cx<double>{0.0, 0.0};
   }
+  if (!do_inverse) return;  // L stays in the lower triangle of A
   __syncthreads();  // Lout read A before the diagonal blocks are overwritten
 
   // ---- inverse: diagonal blocks in place (one wave each)
@@ -332,7 +368,26 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
             acc[r].y += u.y;
           }
         }
-        for (int k = cb_end; k < ri; ++k) {  // finished blocks hold conj(X) above the diagonal
+        // finished blocks hold conj(X) above the diagonal; their values are
+        // loaded kInvBatch at a time so that the loads overlap (one at a time,
+        // every step waited a full memory round trip); same order of sums
+        int k = cb_end;
+        for (; k + kInvBatch <= ri; k += kInvBatch) {
+          cx<double> xb[kInvBatch];
+#pragma unroll
+          for (int u = 0; u < kInvBatch; ++u) xb[u] = A[col + (size_t)(k + u) * lda];
+#pragma unroll
+          for (int u = 0; u < kInvBatch; ++u) {
+            const cx<double> x = {xb[u].x, -xb[u].y};
+#pragma unroll
+            for (int r = 0; r < RQ; ++r) {
+              const cx<double> w = cmul_d(Lr[RQ * g + r][k + u], x);
+              acc[r].x += w.x;
+              acc[r].y += w.y;
+            }
+          }
+        }
+        for (; k < ri; ++k) {
           const cx<double> xc = A[col + (size_t)k * lda];
           const cx<double> x = {xc.x, -xc.y};
 #pragma unroll
@@ -342,27 +397,36 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
             acc[r].y += u.y;
           }
         }
-        cx<double> T[NB];
+        // T[q][col] for q = 0 .. NB-1 arrives in order (lane q / RQ of the
+        // quad holds it in acc[q % RQ]) and is folded into the rows at once,
+        // so no thread holds all NB values (that array went to scratch)
+        cx<double> sm[RQ];
 #pragma unroll
-        for (int r = 0; r < RQ; ++r) {
-          T[r] = quad_bcast<0>(acc[r]);
-          T[RQ + r] = quad_bcast<1>(acc[r]);
-          T[2 * RQ + r] = quad_bcast<2>(acc[r]);
-          T[3 * RQ + r] = quad_bcast<3>(acc[r]);
-        }
+        for (int r = 0; r < RQ; ++r) sm[r] = {0.0, 0.0};
+        auto fold = [&](int q, cx<double> tq) {
+#pragma unroll
+          for (int r = 0; r < RQ; ++r) {
+            const int rr = RQ * g + r;
+            if (q <= rr && rr < ni) {
+              const cx<double> u = cmul_d(Lr[rr][ri + q], tq);
+              sm[r].x += u.x;
+              sm[r].y += u.y;
+            }
+          }
+        };
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) fold(r, quad_bcast<0>(acc[r]));
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) fold(RQ + r, quad_bcast<1>(acc[r]));
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) fold(2 * RQ + r, quad_bcast<2>(acc[r]));
+#pragma unroll
+        for (int r = 0; r < RQ; ++r) fold(3 * RQ + r, quad_bcast<3>(acc[r]));
 #pragma unroll
         for (int r = 0; r < RQ; ++r) {
           const int rr = RQ * g + r;
           if (rr >= ni) break;
-          cx<double> sm = {0.0, 0.0};
-#pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            if (q > rr) break;
-            const cx<double> u = cmul_d(Lr[rr][ri + q], T[q]);
-            sm.x += u.x;
-            sm.y += u.y;
-          }
-          const cx<double> xc = {-sm.x, sm.y};  // conj(X[ri + rr][col])
+          const cx<double> xc = {-sm[r].x, sm[r].y};  // conj(X[ri + rr][col])
           A[col + (size_t)(ri + rr) * lda] = xc;
           C[col + (size_t)(ri + rr) * n] = xc;
         }
@@ -441,16 +505,9 @@ __device__ __forceinline__ void tri_index_desc(int e, int n, int* i, int* j) {
   *i = jj + e;
 }
 
-// 1/sqrt(d) from the hardware estimate, refined by three Newton-Raphson steps
-// y <- y (3/2 - d y^2 / 2); then 1/d = y^2 and sqrt(d) = d y.
+// 1/sqrt(d) (rsq_refined); then 1/d = y^2 and sqrt(d) = d y.
 __device__ __forceinline__ void pivot_terms(double d, double* invr, double* invd, double* r) {
-  double y = __builtin_amdgcn_rsq(d);
-  const double h = 0.5 * d;
-#pragma unroll
-  for (int it = 0; it < 3; ++it) {
-    const double e = fma(-h * y, y, 0.5);
-    y = fma(y, e, y);
-  }
+  const double y = rsq_refined(d);
   *invr = y;
   *invd = y * y;
   *r = d * y;
@@ -626,8 +683,77 @@ __global__ __launch_bounds__(1024) void k_chol_inv_global(const cx<double>* __re
                                                           cx<double>* __restrict__ C,
                                                           int* __restrict__ info,
                                                           const int* __restrict__ prior,
-                                                          int real_only) {
-  chol_inv_body(M, n, s, A, n, A + (size_t)n * n, Lout, C, info, prior, real_only);
+                                                          int real_only, int do_inverse) {
+  chol_inv_body(M, n, s, A, n, A + (size_t)n * n, Lout, C, info, prior, real_only, do_inverse);
+}
+
+// C = L^{-H} for kCholRegMax < n <= 64 R, L (lower triangle, column-major,
+// leading dimension n) in global memory: one wave per column j of
+// X = L^{-1}, many workgroups in parallel (the single-workgroup block inverse
+// took most of the factorisation's time at n = 256).  Forward substitution
+// y = e_j, x_k = y_k / L_kk, y_i -= L_ik x_k (i > k); lane l holds rows
+// l + 64 r.  Column k of L is loaded kTriPrefetch steps ahead (coalesced:
+// consecutive rows on consecutive lanes); rows at or above k read zero.  Row
+// j of C is conj(x), its entries left of the diagonal zero.
+constexpr int kTriPrefetch = 4;
+template <int R>
+__global__ __launch_bounds__(64) void k_tri_inv_wave(const cx<double>* __restrict__ L, int n,
+                                                     cx<double>* __restrict__ C,
+                                                     const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int j = blockIdx.x, lane = threadIdx.x;
+  cx<double> y[R];
+  double inv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = lane + 64 * r;
+    y[r] = {i == j ? 1.0 : 0.0, 0.0};
+    inv[r] = (i >= j && i < n) ? 1.0 / L[i + (size_t)i * n].x : 0.0;
+  }
+  for (int k = lane; k < j; k += 64) C[j + (size_t)k * n] = {0.0, 0.0};
+  constexpr int PD = kTriPrefetch;
+  cx<double> lc[PD][R];
+  // column k of L below the diagonal (zero elsewhere); unconditional loads
+  // from a clamped address, masked when used
+  auto load_col = [&](cx<double> (&dst)[R], int k) {
+    const int kc = k < n ? k : n - 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + 64 * r;
+      const int ic = i < n ? i : n - 1;
+      const cx<double> v = L[ic + (size_t)kc * n];
+      dst[r] = (i > k && i < n && k < n) ? v : cx<double>{0.0, 0.0};
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PD; ++p) load_col(lc[p], j + p);
+  for (int k0 = j; k0 < n; k0 += PD) {
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+      const int k = k0 + p;
+      if (k >= n) break;  // uniform
+      // x_k from the owner of row k (slot k / 64, lane k % 64)
+      const int slot = k >> 6;
+      cx<double> own = y[0];
+      double oinv = inv[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        if (slot == r) {
+          own = y[r];
+          oinv = inv[r];
+        }
+      const int src = k & 63;
+      const cx<double> xk = {bcast_lane(own.x * oinv, src), bcast_lane(own.y * oinv, src)};
+      if (lane == 0) C[j + (size_t)k * n] = {xk.x, -xk.y};
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const cx<double> u = cmul_d(lc[p][r], xk);
+        y[r].x -= u.x;
+        y[r].y -= u.y;
+      }
+      load_col(lc[p], k + PD);
+    }
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_sumsq(const cx<double>* __restrict__ A, long count,
@@ -658,8 +784,22 @@ ace_status chol_inv(ace_ctx c, const cx<double>* M, int n, double s, cx<double>*
     return launch(c, "tri_inv", k_tri_inv, dim3(n), dim3(256), 0, (const cx<double>*)scratch, n,
                   C, (const int*)info_dev);
   }
-  return launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s, scratch,
-                Lout, C, info_dev, prior, real_only ? 1 : 0);
+  // up to 512: Cholesky in one workgroup, then C = L^{-H} one wave per column;
+  // above: the fused single-workgroup form (the wave form's rows per lane grow
+  // with n)
+  const int wave_inverse = n <= 512 ? 1 : 0;
+  ace_status st = launch(c, "chol_inv_global", k_chol_inv_global, dim3(1), dim3(1024), 0, M, n, s,
+                         scratch, Lout, C, info_dev, prior, real_only ? 1 : 0, 1 - wave_inverse);
+  if (st != ACE_OK || !wave_inverse) return st;
+  const cx<double>* Lw = scratch;
+  if (n <= 128)
+    return launch(c, "tri_inv_wave", k_tri_inv_wave<2>, dim3(n), dim3(64), 0, Lw, n, C,
+                  (const int*)info_dev);
+  if (n <= 256)
+    return launch(c, "tri_inv_wave", k_tri_inv_wave<4>, dim3(n), dim3(64), 0, Lw, n, C,
+                  (const int*)info_dev);
+  return launch(c, "tri_inv_wave", k_tri_inv_wave<8>, dim3(n), dim3(64), 0, Lw, n, C,
+                (const int*)info_dev);
 }
 
 ace_status sumsq(ace_ctx c, const cx<double>* A, long count, double s, double* out) {

@@ -253,8 +253,10 @@ __global__ __launch_bounds__(sizeof(TAcc) == 8 ? 512 : 1024) void k_cn_mfma(
 // with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on the
 // 16x16x32 BF16 MFMA with FP32 accumulation (the lo*lo term, ~2^-16 relative,
 // is dropped).  A lane's 8 K slots are 4 consecutive complex grid values.
-// Same workgroup shape and partials as k_cn_mfma.
-__global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restrict__ A, long lda,
+// Same partials as k_cn_mfma; at most kBf16Waves waves per workgroup.
+constexpr int kBf16Stages = 4;
+constexpr int kBf16Waves = 8;
+__global__ __launch_bounds__(64 * kBf16Waves) void k_cn_mfma_bf16x3(const cx<float>* __restrict__ A, long lda,
                                                          int na, const cx<float>* __restrict__ B,
                                                          long ldb, int nb, long K, long kchunk,
                                                          cx<float>* __restrict__ partial,
@@ -273,8 +275,10 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
       cre[x][y] = v4f{0, 0, 0, 0};
       cim[x][y] = v4f{0, 0, 0, 0};
     }
-  // Two-slot pipeline over 16-point steps: the raw loads of step i + 1 are
-  // issued before step i is split into BF16 halves and multiplied.  Loads go
+  // Rolling pipeline over 16-point steps: the raw loads of step i + R - 1 are
+  // issued before step i is split into BF16 halves and multiplied, so R - 1
+  // steps are in flight (two slots left the waves waiting on memory: the
+  // kernel ran at 8% MFMA use and a third of its HBM rate at cfg 2).  Loads go
   // through per-wave buffer resources spanning the tile's rows inside the
   // output: rows outside it fall past the resource and read zero without a
   // memory access, so no load is conditional (a conditional load makes the
@@ -285,8 +289,9 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
       (void*)(A + (size_t)t.a0 * lda), (short)0, (int)((long)nva * lda * 8), kBufferFlags);
   const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(B + (size_t)t.b0 * ldb), (short)0, (int)((long)nvb * ldb * 8), kBufferFlags);
-  float a[2][2][8], b[2][2][8];
-  unsigned kin[2];
+  constexpr int R = kBf16Stages;
+  float a[R][2][8], b[R][2][8];
+  unsigned kin[R];
   auto load = [&](float (&ar)[2][8], float (&br)[2][8], unsigned& in, long k) {
     in = 0;
 #pragma unroll
@@ -306,11 +311,13 @@ __global__ __launch_bounds__(768) void k_cn_mfma_bf16x3(const cx<float>* __restr
       }
     }
   };
-  load(a[0], b[0], kin[0], kbeg + 4 * kq);
-  for (long k0 = kbeg; k0 < kend; k0 += 32) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      load(a[j ^ 1], b[j ^ 1], kin[j ^ 1], k0 + 16 * (j + 1) + 4 * kq);
+  for (int j = 0; j < R - 1; ++j) load(a[j], b[j], kin[j], kbeg + 16 * j + 4 * kq);
+  for (long k0 = kbeg; k0 < kend; k0 += 16 * R) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int nx = (j + R - 1) % R;
+      load(a[nx], b[nx], kin[nx], k0 + 16 * (j + R - 1) + 4 * kq);
       v8bf ahi[2], alo[2], bhi[2], blo[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -719,13 +726,13 @@ static bool herm_shape(int n, long K, int max_waves, int cu_waves, CnShape* s) {
 }
 
 size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
-  CnShape s32 = cn_shape(na, nb, K, 16, 16), s16 = cn_shape(na, nb, K, 12, 12);
+  CnShape s32 = cn_shape(na, nb, K, 16, 16), s16 = cn_shape(na, nb, K, kBf16Waves, kBf16Waves);
   CnShape s64 = cn_shape(na, nb, K, 8, 12);
   long k32 = s32.ks > s16.ks ? s32.ks : s16.ks, k64 = s64.ks;
   if (na == nb) {
     CnShape h;
     if (herm_shape(na, K, 16, 16, &h) && h.ks > k32) k32 = h.ks;
-    if (herm_shape(na, K, 12, 12, &h) && h.ks > k32) k32 = h.ks;
+    if (herm_shape(na, K, kBf16Waves, kBf16Waves, &h) && h.ks > k32) k32 = h.ks;
     if (herm_shape(na, K, 8, 12, &h) && h.ks > k64) k64 = h.ks;
   }
   const size_t b32 = (size_t)k32 * na * nb * sizeof(cx<float>);
@@ -736,8 +743,8 @@ size_t gemm_cn_scratch_bytes(int na, int nb, long K) {
 size_t gemm_cn_partial_bytes(int na, int nb, long K, size_t data_bytes, CnMode mode, bool herm) {
   const bool bf16_split = data_bytes == sizeof(cx<float>) && mode == kBf16Split;
   const bool f64 = data_bytes == sizeof(cx<double>) || mode == kFp64;
-  const int max_waves = f64 ? 8 : bf16_split ? 12 : 16;
-  const int cu_waves = f64 ? 12 : bf16_split ? 12 : 16;
+  const int max_waves = f64 ? 8 : bf16_split ? kBf16Waves : 16;
+  const int cu_waves = f64 ? 12 : bf16_split ? kBf16Waves : 16;
   CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
   if (herm && na == nb) herm_shape(na, K, max_waves, cu_waves, &s);
   const size_t part_eb = f64 ? sizeof(cx<double>) : sizeof(cx<float>);
@@ -754,8 +761,8 @@ ace_status gemm_cn(ace_ctx c, const cx<T>* A, long lda, int na, const cx<T>* B, 
   // resource with 32-bit byte offsets
   if (bf16_split && (lda > (1L << 31) / 256 || ldb > (1L << 31) / 256))
     return fail(c, ACE_E_UNSUPPORTED, "leading dimension too large for the BF16-split product");
-  const int max_waves = f64 ? 8 : bf16_split ? 12 : 16;
-  const int cu_waves = f64 ? 12 : bf16_split ? 12 : 16;
+  const int max_waves = f64 ? 8 : bf16_split ? kBf16Waves : 16;
+  const int cu_waves = f64 ? 12 : bf16_split ? kBf16Waves : 16;
   CnShape s = cn_shape(na, nb, K, max_waves, cu_waves);
   herm = herm && na == nb && herm_shape(na, K, max_waves, cu_waves, &s);
   const int hm = herm ? 1 : 0;
