@@ -55,7 +55,8 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
-FFT_SOURCES = ["paper_1601_07159_amd/csrc/fft_passes.hip", "paper_1601_07159_amd/csrc/fft_core.h"]
+FFT_SOURCES = ["paper_1601_07159_amd/csrc/fft_passes.hip", "paper_1601_07159_amd/csrc/fft_core.h",
+               "paper_1601_07159_amd/csrc/pass_bodies.h"]
 
 
 def fft_source_hash():
