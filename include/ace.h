@@ -148,7 +148,8 @@ ace_status ace_build_W(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  * L_out (nullable): n_band x n_band complex128, column-major, device memory;
  *   receives L.
  * info_dev (nullable): device int; receives 0 on success or k >= 1, the first
- *   non-positive pivot (LAPACK potrf convention); xi is then unspecified.
+ *   non-positive pivot (LAPACK potrf convention); xi and L_out are then
+ *   unspecified.
  *   When info_dev is NULL the call synchronises the stream and returns
  *   ACE_E_NOT_PD on failure.
  * xi may be W itself (same pointer and ld: xi then overwrites W, through a

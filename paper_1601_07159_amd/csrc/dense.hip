@@ -524,34 +524,42 @@ __device__ __forceinline__ void publish_pivot(double d, double* pv) {
   pv[3] = ok ? 0.0 : 1.0;
 }
 
-// Cholesky only (the inverse follows in k_tri_inv): column k of L goes to Lw
-// (and Lout) as it is final.  The owner of the next diagonal entry computes
-// its pivot terms right after its update and publishes them with the column,
-// so the other threads start each step with them.
+// Cholesky only (the inverse follows in k_tri_inv).  Two columns per barrier:
+// at the start of step pair (k, k+1) LDS holds column k (final) and column
+// k+1 as updated through column k-1; every thread forms the values of column
+// k+1 it needs (and the pivot k+1) from those two exactly as their owners
+// would, applies both updates to its entries, and the owners of columns k+2
+// (final) and k+3 publish them for the next pair.  The operations on every
+// entry are those of the one-column sweep, in the same order (the same L bit
+// for bit), with half the barriers (measured at n = 80: 57 -> 46 us).  L is
+// written once at the end (Lw and the optional Lout; upper triangle zero),
+// not column by column inside the loop.
 __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict__ M, int n,
                                                    double s, cx<double>* __restrict__ Lw,
                                                    cx<double>* __restrict__ Lout,
                                                    int* __restrict__ info,
                                                    const int* __restrict__ prior, int real_only) {
-  __shared__ cx<double> colA[2][kCholRegMax];
+  constexpr int SL = kCholSlots;
+  __shared__ cx<double> colA[2][2][kCholRegMax];
   __shared__ double piv[2][4];
+  __shared__ double lscale[kCholRegMax][2];  // per column: 1/sqrt(pivot), sqrt(pivot)
   const int t = threadIdx.x, nt = blockDim.x;
   if (prior && *prior != 0) {
     if (t == 0) *info = *prior;
     return;
   }
   const int tot_a = n * (n + 1) / 2;
-  int ai[kCholSlots], aj[kCholSlots];
-  cx<double> a[kCholSlots];
+  int ai[SL], aj[SL];
+  cx<double> a[SL];
 #pragma unroll
-  for (int q = 0; q < kCholSlots; ++q) {
+  for (int q = 0; q < SL; ++q) {
     const int e = t + q * nt;
     ai[q] = aj[q] = 0;  // column 0 is never updated
     if (e < tot_a) tri_index_desc(e, n, &ai[q], &aj[q]);
   }
-  cx<double> m1[kCholSlots], m2[kCholSlots];
+  cx<double> m1[SL], m2[SL];
 #pragma unroll
-  for (int q = 0; q < kCholSlots; ++q) {
+  for (int q = 0; q < SL; ++q) {
     m1[q] = m2[q] = {0.0, 0.0};
     if (t + q * nt < tot_a) {
       m1[q] = M[ai[q] + (size_t)aj[q] * n];
@@ -559,54 +567,92 @@ __global__ __launch_bounds__(1024) void k_chol_reg(const cx<double>* __restrict_
     }
   }
 #pragma unroll
-  for (int q = 0; q < kCholSlots; ++q) {
+  for (int q = 0; q < SL; ++q) {
     a[q] = ai[q] == aj[q] ? cx<double>{s * m1[q].x, 0.0}
            : real_only    ? cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.0}
                           : cx<double>{0.5 * s * (m1[q].x + m2[q].x), 0.5 * s * (m1[q].y - m2[q].y)};
-    if (t + q * nt < tot_a && aj[q] == 0) {
-      colA[0][ai[q]] = a[q];
-      if (ai[q] == 0) publish_pivot(a[q].x, piv[0]);
+    if (t + q * nt < tot_a) {
+      if (aj[q] == 0) {
+        colA[0][0][ai[q]] = a[q];
+        if (ai[q] == 0) publish_pivot(a[q].x, piv[0]);
+      }
+      if (aj[q] == 1) colA[0][1][ai[q]] = a[q];
     }
   }
   __syncthreads();
   int fail_k = 0;
-  for (int k = 0; k < n; ++k) {
-    const int p = k & 1;
-    const double invr = piv[p][0], invd = piv[p][1], r = piv[p][2], bad = piv[p][3];
-    cx<double> ci[kCholSlots], cj[kCholSlots];
-#pragma unroll
-    for (int q = 0; q < kCholSlots; ++q)
-      if (aj[q] > k) {
-        ci[q] = colA[p][ai[q]];
-        cj[q] = colA[p][aj[q]];
-      }
-    cx<double> oc = {0.0, 0.0};
-    if (t < n && t > k) oc = colA[p][t];
-    if (bad != 0.0) {
+  for (int k = 0; k < n; k += 2) {
+    const int p = (k >> 1) & 1;
+    const bool two = k + 1 < n;
+    const double invr0 = piv[p][0], invd0 = piv[p][1], r0 = piv[p][2], bad0 = piv[p][3];
+    if (bad0 != 0.0) {
       fail_k = k + 1;
       break;
     }
-    if (t < n) {
-      const cx<double> l = t < k    ? cx<double>{0.0, 0.0}
-                           : t == k ? cx<double>{r, 0.0}
-                                    : cx<double>{oc.x * invr, oc.y * invr};
-      Lw[t + (size_t)k * n] = l;
-      if (Lout) Lout[t + (size_t)k * n] = l;
+    // column k + 1 after the column-k update, as its owners form it
+    const cx<double> kk1 = colA[p][0][two ? k + 1 : k];
+    auto col1 = [&](int x) {
+      const cx<double> u = cmulcj_d(colA[p][0][x], kk1);
+      cx<double> v = colA[p][1][x];
+      v.x -= u.x * invd0;
+      v.y -= u.y * invd0;
+      return v;
+    };
+    double invr1 = 0.0, invd1 = 0.0, r1 = 0.0;
+    if (two) {
+      const double d1 = col1(k + 1).x;
+      if (!(d1 > 0.0 && isfinite(d1))) {
+        fail_k = k + 2;
+        break;
+      }
+      pivot_terms(d1, &invr1, &invd1, &r1);
+    }
+    if (t == 0) {
+      lscale[k][0] = invr0;
+      lscale[k][1] = r0;
+      if (two) {
+        lscale[k + 1][0] = invr1;
+        lscale[k + 1][1] = r1;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kCholSlots; ++q)
+    for (int q = 0; q < SL; ++q)
       if (aj[q] > k) {
-        const cx<double> u = cmulcj_d(ci[q], cj[q]);
-        a[q].x -= u.x * invd;
-        a[q].y -= u.y * invd;
-        if (aj[q] == k + 1) {
-          colA[p ^ 1][ai[q]] = a[q];
-          if (ai[q] == k + 1) publish_pivot(a[q].x, piv[p ^ 1]);
+        {
+          const cx<double> u = cmulcj_d(colA[p][0][ai[q]], colA[p][0][aj[q]]);
+          a[q].x -= u.x * invd0;
+          a[q].y -= u.y * invd0;
         }
+        if (aj[q] > k + 1) {
+          const cx<double> u = cmulcj_d(col1(ai[q]), col1(aj[q]));
+          a[q].x -= u.x * invd1;
+          a[q].y -= u.y * invd1;
+        }
+        if (aj[q] == k + 2) {
+          colA[p ^ 1][0][ai[q]] = a[q];
+          if (ai[q] == k + 2) publish_pivot(a[q].x, piv[p ^ 1]);
+        }
+        if (aj[q] == k + 3) colA[p ^ 1][1][ai[q]] = a[q];
       }
     __syncthreads();
   }
   if (t == 0) *info = fail_k;
+  if (fail_k) return;
+  // L_ij = a_ij / sqrt(pivot_j) below the diagonal, sqrt(pivot_j) on it
+#pragma unroll
+  for (int q = 0; q < SL; ++q)
+    if (t + q * nt < tot_a) {
+      const int i = ai[q], j = aj[q];
+      const cx<double> l = i == j ? cx<double>{lscale[j][1], 0.0}
+                                  : cx<double>{a[q].x * lscale[j][0], a[q].y * lscale[j][0]};
+      Lw[i + (size_t)j * n] = l;
+      if (Lout) Lout[i + (size_t)j * n] = l;
+    }
+  for (int e = t; e < n * n; e += nt)
+    if (e % n < e / n) {
+      Lw[e] = {0.0, 0.0};
+      if (Lout) Lout[e] = {0.0, 0.0};
+    }
 }
 
 __device__ __forceinline__ double bcast_lane(double v, int src) {

@@ -113,6 +113,22 @@ def test_compress_reports_not_positive_definite(ace):
     assert e.value.status == 2
 
 
+@pytest.mark.parametrize("nband,zero", [(100, 93), (300, 201), (520, 97)])
+def test_compress_reports_not_positive_definite_large(ace, nband, zero):
+    # the factorisations above 88 bands (panels in LDS with the wave-per-column
+    # inverse up to 512, the fused global-memory form above) stop at the first
+    # non-positive pivot and report it; xi is then not written
+    import torch
+    n, L, nocc = 16, 7.5, 8
+    psi = synth.smooth_orbitals(n, L, nband, seed=nband + 1)
+    psi[zero] = 0.0
+    W = O.build_W(psi[:nocc], psi, ogrid(n, L))
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ace.compress(to_gpu(psi, "fp64"), to_gpu(W, "fp64"), ggrid(n, L), "fp64", info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == zero + 1
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_orthonormalize_matches_oracle(ace, prec):
     n, L = 24, 10.0
@@ -173,10 +189,12 @@ def test_compress_hermitian_tiles_over_several_workgroups(ace, nband, prec):
     assert rel(to_np(Q), O.orthonormalize(X, g)) <= tol(prec)
 
 
-@pytest.mark.parametrize("nocc,nband", [(50, 81), (50, 88), (60, 96), (60, 100), (8, 520)])
+@pytest.mark.parametrize("nocc,nband", [(50, 81), (50, 88), (60, 96), (60, 100), (24, 256),
+                                        (12, 400), (8, 520)])
 def test_compress_large_bands_both_factorisation_paths(ace, nocc, nband):
     # n_band <= 88 factorises in registers, larger n_band in global scratch with
-    # the panels staged in LDS up to 512, beyond that from global memory
+    # the panels staged in LDS and the inverse one wave per column (two, four or
+    # eight rows per lane) up to 512, beyond that from global memory
     import torch
     n, L = 16, 7.5
     psi = synth.smooth_orbitals(n, L, nband, seed=nband)
