@@ -11,23 +11,22 @@ namespace ace {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Fused factorisation of a Hermitian matrix, one workgroup:
+// Factorisation of a Hermitian matrix, one workgroup:
 //   A = s (M + M^H)/2  (lower triangle),  A = L L^H  (Cholesky),
-//   optional copy of L,  C = L^{-H}  (upper triangular).
+//   optional copy of L,  and with do_inverse C = L^{-H} (upper triangular).
 // This form serves n above kCholRegMax (the register form below covers the
-// smaller ones), with A in global scratch.  Blocked in panels of kCholNB columns so that only a few workgroup barriers
-// are needed per panel:
+// smaller ones), with A in global scratch.  Blocked in panels of kCholNB
+// columns so that only a few workgroup barriers are needed per panel:
 //   Cholesky  the diagonal block is factored by wave 0 alone (lanes of one
 //             wave stay ordered without barriers), the rows below solve
 //             x L_kk^H = a one thread per row, the trailing lower triangle is
 //             updated with kCholNB-term dot products.
-//   inverse   X = L^{-1}: diagonal blocks inverted in place, one wave each;
+//   inverse   (n > kCholPanelRows; below, k_tri_inv_wave follows instead)
+//             X = L^{-1}: diagonal blocks inverted in place, one wave each;
 //             then block row i: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj, with the
 //             finished blocks of X kept (conjugate-transposed) in C.
 // lda >= n; T is scratch of kCholNB x n.
 constexpr int kCholNB = 16;
-// Loads in flight per thread in the inverse's block-row products.
-constexpr int kInvBatch = 8;
 // Up to this n the current panel (n x kCholNB) is staged in LDS.
 constexpr int kCholPanelRows = 512;
 __shared__ cx<double> chol_panel[kCholNB][kCholPanelRows];
@@ -45,18 +44,6 @@ __device__ __forceinline__ cx<double> cmulcj_d(cx<double> a, cx<double> b) {
   return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-// value of lane J of this lane's quad (DPP quad_perm [J,J,J,J])
-template <int J>
-__device__ __forceinline__ double quad_bcast(double v) {
-  const long long u = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffLL), J * 0x55, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), J * 0x55, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-template <int J>
-__device__ __forceinline__ cx<double> quad_bcast(cx<double> v) {
-  return {quad_bcast<J>(v.x), quad_bcast<J>(v.y)};
-}
 
 // 1/sqrt(d) from the hardware estimate, refined by three Newton-Raphson steps
 // y <- y (3/2 - d y^2 / 2).
@@ -336,105 +323,7 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
     }
   for (int ib = 1; ib < nbk; ++ib) {
     const int ri = ib * NB, ni = n - ri < NB ? n - ri : NB;
-    if (n <= kCholPanelRows) {
-      // block row ib of L (columns < ri) and X_ii staged in LDS:
-      // Lr[r][k] = L[ri + r][k] for k < ri, Lr[r][ri + q] = X_ii[r][q] (q <= r)
-      cx<double> (*Lr)[kCholPanelRows] = chol_panel;
-      const int w = ri + ni;
-      for (int e = t; e < ni * w; e += nt) {
-        const int r = e / w, k = e - r * w;
-        Lr[r][k] = A[(ri + r) + (size_t)k * lda];
-      }
-      __syncthreads();
-      // four threads (a lane quad) per column, each with four rows r of the
-      // block row: T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]; the
-      // quad then shares its T values through DPP broadcasts and each thread
-      // forms X[ri + r][col] = -sum_{q <= r} X_ii[r][q] T[q][col] for its rows.
-      // (All four lanes of a quad take the same trip counts: 4 ri and the
-      // workgroup size are multiples of 4.)
-      constexpr int RQ = NB / 4;
-      for (int e = t; e < 4 * ri; e += nt) {
-        const int col = e >> 2, g = e & 3;
-        cx<double> acc[RQ];
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) acc[r] = {0.0, 0.0};
-        const int cb_end = (col / NB + 1) * NB;  // <= ri: X[k][col] for k < cb_end is diagonal
-        for (int k = col; k < cb_end; ++k) {   // the diagonal block holds X in place
-          const cx<double> x = A[k + (size_t)col * lda];
-#pragma unroll
-          for (int r = 0; r < RQ; ++r) {
-            const cx<double> u = cmul_d(Lr[RQ * g + r][k], x);
-            acc[r].x += u.x;
-            acc[r].y += u.y;
-          }
-        }
-        // finished blocks hold conj(X) above the diagonal; their values are
-        // loaded kInvBatch at a time so that the loads overlap (one at a time,
-        // every step waited a full memory round trip); same order of sums
-        int k = cb_end;
-        for (; k + kInvBatch <= ri; k += kInvBatch) {
-          cx<double> xb[kInvBatch];
-#pragma unroll
-          for (int u = 0; u < kInvBatch; ++u) xb[u] = A[col + (size_t)(k + u) * lda];
-#pragma unroll
-          for (int u = 0; u < kInvBatch; ++u) {
-            const cx<double> x = {xb[u].x, -xb[u].y};
-#pragma unroll
-            for (int r = 0; r < RQ; ++r) {
-              const cx<double> w = cmul_d(Lr[RQ * g + r][k + u], x);
-              acc[r].x += w.x;
-              acc[r].y += w.y;
-            }
-          }
-        }
-        for (; k < ri; ++k) {
-          const cx<double> xc = A[col + (size_t)k * lda];
-          const cx<double> x = {xc.x, -xc.y};
-#pragma unroll
-          for (int r = 0; r < RQ; ++r) {
-            const cx<double> u = cmul_d(Lr[RQ * g + r][k], x);
-            acc[r].x += u.x;
-            acc[r].y += u.y;
-          }
-        }
-        // T[q][col] for q = 0 .. NB-1 arrives in order (lane q / RQ of the
-        // quad holds it in acc[q % RQ]) and is folded into the rows at once,
-        // so no thread holds all NB values (that array went to scratch)
-        cx<double> sm[RQ];
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) sm[r] = {0.0, 0.0};
-        auto fold = [&](int q, cx<double> tq) {
-#pragma unroll
-          for (int r = 0; r < RQ; ++r) {
-            const int rr = RQ * g + r;
-            if (q <= rr && rr < ni) {
-              const cx<double> u = cmul_d(Lr[rr][ri + q], tq);
-              sm[r].x += u.x;
-              sm[r].y += u.y;
-            }
-          }
-        };
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) fold(r, quad_bcast<0>(acc[r]));
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) fold(RQ + r, quad_bcast<1>(acc[r]));
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) fold(2 * RQ + r, quad_bcast<2>(acc[r]));
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) fold(3 * RQ + r, quad_bcast<3>(acc[r]));
-#pragma unroll
-        for (int r = 0; r < RQ; ++r) {
-          const int rr = RQ * g + r;
-          if (rr >= ni) break;
-          const cx<double> xc = {-sm[r].x, sm[r].y};  // conj(X[ri + rr][col])
-          A[col + (size_t)(ri + rr) * lda] = xc;
-          C[col + (size_t)(ri + rr) * n] = xc;
-        }
-      }
-      __syncthreads();
-      continue;
-    }
-    // n > kCholPanelRows: everything from global memory
+    // (the inverse runs here only above kCholPanelRows: from global memory)
     // T[r][col] = sum_{k = col}^{ri-1} L[ri + r][k] X[k][col]
     for (int col = wave; col < ri; col += nw)
       for (int r = lane; r < ni; r += 64) {
