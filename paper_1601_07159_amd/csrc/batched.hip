@@ -239,8 +239,11 @@ struct Bucket {
 // Tasks of the recorded launches: the launches of the members interleave (the
 // s-th launch of every member, then the (s+1)-th ...), so every task comes
 // after the tasks it waits for (the previous launch of its instance).  A
-// launch is cut into tasks of up to 16 steps, about two tasks per workgroup
-// when it is large.
+// launch is cut into tasks of up to kMaxTaskSteps steps, about one task per
+// workgroup when it is large (every task ends with a release, which writes
+// back the XCD's L2).
+constexpr long kMaxTaskSteps = 64;
+
 std::vector<ace_ptask> make_tasks(const Bucket& bk, const std::vector<ace_plaunch>& L,
                                   const std::vector<int>& first) {
   std::vector<ace_ptask> tasks;
@@ -256,8 +259,8 @@ std::vector<ace_ptask> make_tasks(const Bucket& bk, const std::vector<ace_plaunc
       const ace_plaunch& l = L[li];
       const long step = persist_step(bk.n, bk.eb, l.kind);
       const long iters = (l.units + step - 1) / step;
-      const long per = std::max<long>(1, std::min<long>(16, (iters + 2L * bk.grid - 1) /
-                                                                 (2L * bk.grid)));
+      const long per = std::max<long>(
+          1, std::min<long>(kMaxTaskSteps, (iters + bk.grid - 1) / bk.grid));
       for (long it = 0; it < iters; it += per) {
         ace_ptask t{};
         t.launch = li;

@@ -156,8 +156,10 @@ __global__ __launch_bounds__((PShape<N, T, AccQ>::kThreads)) void k_build_persis
         }
         break;
     }
-    // every thread's results reach device scope before the task is counted
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the workgroup's results are published by wave 0's release at the next
+    // take (after this barrier), as in a grid barrier; a release fence in
+    // every wave cost a write-back of the XCD's L2 per wave and task (cfg 4:
+    // 115 ms of 427)
     __syncthreads();
     prev = tk.launch;
   }
