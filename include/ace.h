@@ -288,11 +288,13 @@ ace_status ace_rayleigh_ritz(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  *     kernel and leaves NaN in W, which the compression reports as a failed
  *     factorisation.
  * The compressions run on the branch streams.  The whole batch is captured
- * into one HIP graph that is launched on the context stream.  A later call with an identical instance array (same
- * pointers, sizes and settings) replays that graph without re-enqueueing; the
- * data behind the pointers may change between calls.  Pointers must not
- * overlap across instances' outputs; xi may not alias W here.  Never
- * synchronises.
+ * into one HIP graph that is launched on the context stream.  A later call
+ * with an identical instance array (same pointers, sizes and settings)
+ * replays that graph without re-enqueueing and never synchronises; the data
+ * behind the pointers may change between calls.  A call that captures anew
+ * may wait for the context stream (when the workspace grows, and before the
+ * task lists of the previous persistent graph are freed).  Pointers must not
+ * overlap across instances' outputs; xi may not alias W here.
  */
 typedef struct {
   ace_grid grid;
