@@ -198,9 +198,8 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 enum PassKind { kPassTable = 0, kPassSlab = 1, kPassPlane = 2, kPassAccum = 3, kPassAccumQ = 4 };
 
 // Persistent batched kernel (persist.hip) for grid size n and element bytes eb
-// (8: complex64, 16: complex128): threads per workgroup, units per step of a
-// pass kind, and the co-resident workgroups per CU.
-int persist_threads(int n, size_t eb);
+// (8: complex64, 16: complex128): units per step of a pass kind, and the
+// co-resident workgroups per CU.
 int persist_step(int n, size_t eb, int kind);
 ace_status persist_blocks_per_cu(ace_ctx c, int n, size_t eb, bool accq, int* out);
 // Enqueues (on c->stream) the reset of ctl/done, the persistent kernel over

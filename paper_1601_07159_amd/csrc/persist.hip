@@ -204,15 +204,6 @@ ace_status occupancy_n(ace_ctx c, int* out) {
 
 }  // namespace
 
-int persist_threads(int n, size_t eb) {
-#define ACE_CASE(NV)                                                                \
-  if (n == NV)                                                                      \
-    return eb == 16 ? PShape<NV, double, false>::kThreads : PShape<NV, float, false>::kThreads;
-  ACE_FOR_EACH_N(ACE_CASE)
-#undef ACE_CASE
-  return 0;
-}
-
 int persist_step(int n, size_t eb, int kind) {
 #define ACE_CASE(NV)                                                                 \
   if (n == NV) {                                                                     \
