@@ -11,21 +11,33 @@
 #include "../../include/ace.h"
 #include "fft_core.h"
 
+// The scaled kernel of one build, K'(G) = coef * K(G) (times *dscale when
+// dscale is set), evaluated on the fly from the per-axis factors
+// (2 pi / L_a)^2: K = 4 pi / |G|^2 for G != 0, times -expm1(-|G|^2 / (4 mu^2))
+// for the screened kernel; K(0) = g0; |G|^2 / 2 for the kinetic kind.
+struct ace_kspec {
+  double t2[3];          // (2 pi / L_a)^2
+  double coef;
+  double inv4mu2;        // 1 / (4 mu^2), screened kernel
+  double g0;
+  const double* dscale;  // nullable device factor (read by every thread)
+  int n;
+  int kind;
+};
+
 // One pass launch of a build, recorded for the persistent batched kernel
 // (plain data, copied to device memory).
 struct ace_plaunch {
   int kind;  // ace::PassKind
   int mode, i0, A, j0, nbc, accumulate, npairs;
   long p0;
-  long units;  // logical units of the launch (grid points, slabs, planes, pencil tiles)
+  long units;  // logical units of the launch (slabs, planes, pencil tiles)
   const void* phi;
   const void* psi;
   void* buf;
   void* W;
-  void* Kt;
   long ldphi, ldpsi, ldW;
-  int n, table_kind;
-  double L0, L1, L2, mu, g0, coef;
+  ace_kspec ks;  // plane pass
 };
 
 // One task of the persistent kernel: units [u0, u1) of launch `launch`, run
@@ -195,7 +207,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 
 // Pass kinds of a recorded launch.
-enum PassKind { kPassTable = 0, kPassSlab = 1, kPassPlane = 2, kPassAccum = 3, kPassAccumQ = 4 };
+enum PassKind { kPassSlab = 1, kPassPlane = 2, kPassAccum = 3, kPassAccumQ = 4 };
 
 // Persistent batched kernel (persist.hip) for grid size n and element bytes eb
 // (8: complex64, 16: complex128): units per step of a pass kind, and the

@@ -17,7 +17,8 @@
 //                         phi_i, accumulate in thread-private LDS; w_j is
 //                         written once per block (no atomics, no barriers).
 // The 1/N_g of the inverse transform, the minus sign and the caller's scale are
-// folded into the kernel table K'(G) = -scale K(G) / N_g.
+// folded into the scaled kernel K'(G) = -scale K(G) / N_g, evaluated on the fly
+// in the plane pass from the per-axis factors (2 pi / L_a)^2 (no N_g table).
 #include <cmath>
 
 #include <vector>
@@ -29,15 +30,6 @@ namespace ace {
 
 namespace {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_kernel_table(T* __restrict__ Kt, int n, double L0,
-                                                      double L1, double L2, int kind, double mu,
-                                                      double g0, double coef,
-                                                      const double* __restrict__ dscale) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (long)n * n * n) return;
-  kernel_table_at<T>(Kt, idx, n, L0, L1, L2, kind, mu, g0, coef, dscale);
-}
 
 // Forward slab pass: one group of N threads per (x0, pair).
 template <int N, typename T, int P>
@@ -56,12 +48,12 @@ __global__ __launch_bounds__(N * P) void k_pair_fwd_slab_t1(const cx<T>* __restr
 // Plane pass: one group of N threads per (k1 plane, pair).
 template <int N, typename T, int P>
 __global__ __launch_bounds__(N * P) void k_plane_kernel_t1(cx<T>* __restrict__ buf,
-                                                        const T* __restrict__ Kt, int npairs) {
+                                                        ace_kspec ks, int npairs) {
   __shared__ cx<T> s_all[P * N * (N + 1)];
   const long total = (long)N * npairs;
   const long lid0 = xcd_logical(blockIdx.x, gridDim.x) * P;
   if (lid0 >= total) return;  // the whole workgroup
-  plane_t1_body<N, T, P>(s_all, (int)threadIdx.x, false, lid0, total, buf, Kt, npairs);
+  plane_t1_body<N, T, P>(s_all, (int)threadIdx.x, false, lid0, total, buf, ks, npairs);
 }
 
 // The slab and plane passes split every line FFT over the 4 lanes of a quad
@@ -155,7 +147,7 @@ __global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict
 // store of the plane.
 template <int N, typename T>
 __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
-                                                        const T* __restrict__ Kt, int npairs) {
+                                                        ace_kspec ks, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = kQuadLd<N>;
   constexpr int M = N / 4;
@@ -188,12 +180,15 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
     for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + l];
   }
   fft_quad_d2b<N, -1, T>(v, h);
-  const T* kcol = Kt + (size_t)k1 * N + l;
+  {
+    const KEval<T> ke(ks);
+    const T s12 = ke.part12(k1, l);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const T kk = kcol[(size_t)quad_block_index(k, M, h) * NN];
-    v[k].x *= kk;
-    v[k].y *= kk;
+    for (int k = 0; k < M; ++k) {
+      const T kk = ke.at(quad_block_index(k, M, h), s12);
+      v[k].x *= kk;
+      v[k].y *= kk;
+    }
   }
   fft_quad_b2d<N, +1, T>(v, h);
   if constexpr (kQuadStage<N>) __syncthreads();  // every column read before any is rewritten
@@ -288,8 +283,7 @@ __global__ __launch_bounds__(64 * kRowWaves<N>) void k_pair_fwd_slab_row(
 // store of the plane.
 template <int N, typename T>
 __global__ __launch_bounds__(64 * kRowWaves<N>) void k_plane_kernel_row(cx<T>* __restrict__ buf,
-                                                                   const T* __restrict__ Kt,
-                                                                   int npairs) {
+                                                                   ace_kspec ks, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = kRowLd<N>;
   constexpr int M = N / 4;
@@ -308,12 +302,15 @@ __global__ __launch_bounds__(64 * kRowWaves<N>) void k_plane_kernel_row(cx<T>* _
 #pragma unroll
   for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 4 * m) * NN + lc];
   fft_quad_d2b<N, -1, T, 16>(v, h);
-  const T* kcol = Kt + (size_t)k1 * N + lc;
+  {
+    const KEval<T> ke(ks);
+    const T s12 = ke.part12(k1, lc);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const T kk = kcol[(size_t)quad_block_index(k, M, h) * NN];
-    v[k].x *= kk;
-    v[k].y *= kk;
+    for (int k = 0; k < M; ++k) {
+      const T kk = ke.at(quad_block_index(k, M, h), s12);
+      v[k].x *= kk;
+      v[k].y *= kk;
+    }
   }
   fft_quad_b2d<N, +1, T, 16>(v, h);
   if (live) {
@@ -398,7 +395,7 @@ __global__ __launch_bounds__(8 * N) void k_pair_fwd_slab_oct(const cx<T>* __rest
 
 template <int N, typename T>
 __global__ __launch_bounds__(8 * N) void k_plane_kernel_oct(cx<T>* __restrict__ buf,
-                                                            const T* __restrict__ Kt, int npairs) {
+                                                            ace_kspec ks, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = kOctLd<N>;
   constexpr int M = N / 8;
@@ -416,12 +413,15 @@ __global__ __launch_bounds__(8 * N) void k_plane_kernel_oct(cx<T>* __restrict__ 
 #pragma unroll
   for (int m = 0; m < M; ++m) v[m] = plane[(size_t)(h + 8 * m) * NN + l];
   fft_oct_d2b<N, -1, T>(v, h, tw);
-  const T* kcol = Kt + (size_t)k1 * N + l;
+  {
+    const KEval<T> ke(ks);
+    const T s12 = ke.part12(k1, l);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const T kk = kcol[(size_t)oct_block_index(k, M, h) * NN];
-    v[k].x *= kk;
-    v[k].y *= kk;
+    for (int k = 0; k < M; ++k) {
+      const T kk = ke.at(oct_block_index(k, M, h), s12);
+      v[k].x *= kk;
+      v[k].y *= kk;
+    }
   }
   fft_oct_b2d<N, +1, T>(v, h, tw);
 #pragma unroll
@@ -732,7 +732,7 @@ k_pencil_accum_real_sym(const T* __restrict__ phi,
 // pair j, i has the same sum because K(G) = K(-G)).
 template <int N, typename T>
 __global__ __launch_bounds__(256) void k_pencil_energy(const cx<T>* __restrict__ buf,
-                                                       const T* __restrict__ Kt, long p0,
+                                                       ace_kspec ks, long p0,
                                                        double* __restrict__ partial) {
   constexpr int NN = N * N;
   constexpr int TILES = (NN + 63) / 64;
@@ -754,9 +754,11 @@ __global__ __launch_bounds__(256) void k_pencil_energy(const cx<T>* __restrict__
     for (int m = 0; m < M; ++m) v[m] = base[(size_t)(h + 4 * m) * NN];
     fft_quad_d2b<N, -1, T, 16>(v, h);
     if (q < NN) {
+      const KEval<T> ke(ks);
+      const T s12 = ke.part12(q / N, q - (q / N) * N);
 #pragma unroll
       for (int k = 0; k < M; ++k) {
-        const double kk = (double)Kt[(size_t)quad_block_index(k, M, h) * NN + q];
+        const double kk = (double)ke.at(quad_block_index(k, M, h), s12);
         sum += kk * ((double)v[k].x * v[k].x + (double)v[k].y * v[k].y);
       }
     }
@@ -823,8 +825,7 @@ long energy_chunk(ace_ctx c, const GridInfo& g, size_t eb, int nocc) {
 size_t energy_direct_ws_bytes(ace_ctx c, const GridInfo& g, size_t eb, int nocc) {
   const long total = (long)nocc * (nocc + 1) / 2;
   const long tiles = ((long)g.n * g.n + 63) / 64;
-  return align_up((size_t)g.ng * (eb / 2), 256) +
-         align_up(((size_t)total * tiles + kSumBlocks) * sizeof(double), 256) +
+  return align_up(((size_t)total * tiles + kSumBlocks) * sizeof(double), 256) +
          align_up((size_t)energy_chunk(c, g, eb, nocc) * g.ng * eb, 256);
 }
 
@@ -888,8 +889,7 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
   pl.B = B;
   pl.A = (int)std::max<long>(1, std::min<long>(nocc, maxpairs / B));
   pl.pairs_alloc = std::max<size_t>((size_t)pl.A * pl.B, (size_t)sym_alloc);
-  pl.bytes = align_up((size_t)g.ng * std::max<size_t>(eb / 2, 4), 256) +
-             align_up(pl.pairs_alloc * pair_bytes, 256);
+  pl.bytes = align_up(pl.pairs_alloc * pair_bytes, 256);
   return pl;
 }
 
@@ -930,36 +930,25 @@ BuildPlan plan_build_real(ace_ctx c, const GridInfo& g, size_t cx_bytes, int noc
     pl.sym = false;
     pl.pairs_alloc = (size_t)((pl.A + 1) / 2) * pl.B;
   }
-  pl.bytes = align_up((size_t)g.ng * std::max<size_t>(cx_bytes / 2, 4), 256) +
-             align_up(pl.pairs_alloc * unit_bytes, 256);
+  pl.bytes = align_up(pl.pairs_alloc * unit_bytes, 256);
   return pl;
 }
 
 namespace {
 
-template <typename T>
-ace_status make_kernel_table(ace_ctx c, const GridInfo& g, T* Kt, double coef,
-                             const double* dscale = nullptr) {
-  if (c->record) {
-    if (dscale) return fail(c, ACE_E_UNSUPPORTED, "recorded build with a device scale");
-    ace_plaunch l{};
-    l.kind = kPassTable;
-    l.units = g.ng;
-    l.Kt = Kt;
-    l.n = g.n;
-    l.table_kind = g.kind;
-    l.L0 = g.L[0];
-    l.L1 = g.L[1];
-    l.L2 = g.L[2];
-    l.mu = g.mu;
-    l.g0 = g.g0;
-    l.coef = coef;
-    c->record->push_back(l);
-    return ACE_OK;
-  }
-  const unsigned blocks = (unsigned)((g.ng + 255) / 256);
-  return launch(c, "kernel_table", k_kernel_table<T>, dim3(blocks), dim3(256), 0, Kt, g.n, g.L[0],
-                g.L[1], g.L[2], g.kind, g.mu, g.g0, coef, dscale);
+// The scaled kernel K'(G) = coef * K(G) (* *dscale) of a grid, for the plane
+// and energy passes, which evaluate it on the fly.
+ace_kspec kspec_of(const GridInfo& g, double coef, const double* dscale = nullptr) {
+  ace_kspec k{};
+  const double twopi = 6.283185307179586477;
+  for (int a = 0; a < 3; ++a) k.t2[a] = (twopi / g.L[a]) * (twopi / g.L[a]);
+  k.coef = coef;
+  k.inv4mu2 = g.kind == ACE_ERFC ? 1.0 / (4.0 * g.mu * g.mu) : 0.0;
+  k.g0 = g.g0;
+  k.dscale = dscale;
+  k.n = g.n;
+  k.kind = g.kind;
+  return k;
 }
 
 // Line shape of the slab and plane passes: one thread per line (1), a lane
@@ -1039,13 +1028,13 @@ ace_status fwd_slab(ace_ctx c, const cx<T>* phi, long ldphi, const cx<T>* psi, l
 }
 
 template <int N, typename T>
-ace_status plane(ace_ctx c, cx<T>* buf, const T* Kt, int np) {
+ace_status plane(ace_ctx c, cx<T>* buf, const ace_kspec& ks, int np) {
   if (c->record) {
     ace_plaunch l{};
     l.kind = kPassPlane;
     l.units = (long)N * np;
     l.buf = buf;
-    l.Kt = (void*)Kt;
+    l.ks = ks;
     l.npairs = np;
     c->record->push_back(l);
     return ACE_OK;
@@ -1054,16 +1043,16 @@ ace_status plane(ace_ctx c, cx<T>* buf, const T* Kt, int np) {
   const int form = pass_form<N, T>(c, true);
   if constexpr (kOctOk<N, T>)
     if (form == 8)
-      return launch(c, "plane_kernel", k_plane_kernel_oct<N, T>, grid, dim3(8 * N), 0, buf, Kt,
+      return launch(c, "plane_kernel", k_plane_kernel_oct<N, T>, grid, dim3(8 * N), 0, buf, ks,
                     np);
   if (form == 16)
     return launch(c, "plane_kernel", k_plane_kernel_row<N, T>, grid, dim3(64 * kRowWaves<N>), 0,
-                  buf, Kt, np);
+                  buf, ks, np);
   if (form == 4)
-    return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, Kt, np);
+    return launch(c, "plane_kernel", k_plane_kernel<N, T>, grid, dim3(4 * N), 0, buf, ks, np);
   constexpr int P = t1_group<N, T>(80 * 1024);
   return launch(c, "plane_kernel", k_plane_kernel_t1<N, T, P>,
-                dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, buf, Kt, np);
+                dim3(xcd_pad(((long)N * np + P - 1) / P)), dim3(N * P), 0, buf, ks, np);
 }
 
 // Form of the accumulate pass: one thread per pencil with the accumulator in
@@ -1125,20 +1114,19 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
   const int A = pl.A, B = pl.B;
   const bool sym = pl.sym;
   const size_t pairs_alloc = pl.pairs_alloc;
-  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
   if ((st = ws_begin(c, pl.bytes)) != ACE_OK) return st;
-  T* Kt = (T*)ws_take(c, kt_bytes, &st);
   cx<T>* buf = (cx<T>*)ws_take(c, pairs_alloc * pair_bytes, &st);
-  if (!Kt || !buf) return st;
-  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
+  if (!buf) return st;
+  if (c->record && dscale) return fail(c, ACE_E_UNSUPPORTED, "recorded build with a device scale");
+  const ace_kspec ks = kspec_of(g, -scale / (double)g.ng, dscale);
   int jstart = 0;
   if (pl.merged) {
     const long all = (long)nocc * (nocc + 1) / 2 + (long)nocc * (nband - nocc);
     if ((st = fwd_slab<N, T>(c, phi, ldphi, psi, ldpsi, buf, 3, 0, nocc, nocc, 0L,
                              (int)all)) != ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, buf, Kt, (int)all)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, ks, (int)all)) != ACE_OK) return st;
     return accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nband, acc0, 3);
   }
   if (sym && pl.symblk == 0) {
@@ -1148,7 +1136,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
     if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, 0L, (int)tri)) !=
         ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, buf, Kt, (int)tri)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, ks, (int)tri)) != ACE_OK) return st;
     if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, 0, nocc, 0, nocc, acc0, 1)) != ACE_OK)
       return st;
     jstart = nocc;
@@ -1166,7 +1154,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
           if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, i0, 1, i0, 0L, np)) !=
               ACE_OK)
             return st;
-          if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
+          if ((st = plane<N, T>(c, buf, ks, np)) != ACE_OK) return st;
           if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, i0, ni, (int)started[I], 1)) !=
               ACE_OK)
             return st;
@@ -1176,7 +1164,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
           if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 0, i0, ni, j0, 0L, np)) !=
               ACE_OK)
             return st;
-          if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
+          if ((st = plane<N, T>(c, buf, ks, np)) != ACE_OK) return st;
           // bands of J from the orbitals of I, then bands of I from those of J
           if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, ni, j0, nj, (int)started[J], 0)) !=
               ACE_OK)
@@ -1198,7 +1186,7 @@ ace_status build_W_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int nocc, l
       if ((st = fwd_slab<N, T>(c, phi, ldphi, psi, ldpsi, buf, 0, i0, Ac, j0, 0L, np)) !=
           ACE_OK)
         return st;
-      if ((st = plane<N, T>(c, buf, Kt, np)) != ACE_OK) return st;
+      if ((st = plane<N, T>(c, buf, ks, np)) != ACE_OK) return st;
       if ((st = accum<N, T>(c, phi, ldphi, buf, W, ldW, i0, Ac, j0, Bc, (i0 > 0 || accumulate) ? 1 : 0, 0)) !=
           ACE_OK)
         return st;
@@ -1218,19 +1206,17 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
   const bool sym_ok = sizeof(T) == 4 || N <= 48;
   const BuildPlan pl =
       plan_build_real(c, g, sizeof(cx<T>), nocc, nband, sym_ok && psi == phi && ldpsi == ldphi);
-  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   ace_status st;
   if ((st = ws_begin(c, pl.bytes)) != ACE_OK) return st;
-  T* Kt = (T*)ws_take(c, kt_bytes, &st);
   cx<T>* buf = (cx<T>*)ws_take(c, pl.pairs_alloc * unit_bytes, &st);
-  if (!Kt || !buf) return st;
-  if ((st = make_kernel_table<T>(c, g, Kt, -scale / (double)g.ng, dscale)) != ACE_OK) return st;
+  if (!buf) return st;
+  const ace_kspec ks = kspec_of(g, -scale / (double)g.ng, dscale);
   if (pl.sym) {
     const int G = (nocc + 1) / 2, nu = (int)pl.pairs_alloc;
     if ((st = launch(c, "pair_fwd_real", k_pair_fwd_real_t1<N, T>, dim3(xcd_pad((long)N * nu)),
                      dim3(N), 0, phi, ldphi, psi, ldpsi, buf, 0, nocc, G, nocc, nu, 1)) != ACE_OK)
       return st;
-    if ((st = plane<N, T>(c, buf, Kt, nu)) != ACE_OK) return st;
+    if ((st = plane<N, T>(c, buf, ks, nu)) != ACE_OK) return st;
     const int nrows = G + (nband - nocc);
     return launch(c, "pencil_accum_real", k_pencil_accum_real_sym<N, T>,
                   dim3(xcd_pad((long)TILES * nrows)), dim3(64), 0, phi, ldphi, (const cx<T>*)buf,
@@ -1246,7 +1232,7 @@ ace_status build_W_real_n(ace_ctx c, const GridInfo& g, const T* phi, int nocc, 
                        dim3(xcd_pad((long)N * nu)), dim3(N), 0, phi, ldphi, psi, ldpsi, buf, i0,
                        Ac, Am, j0, nu, 0)) != ACE_OK)
         return st;
-      if ((st = plane<N, T>(c, buf, Kt, nu)) != ACE_OK) return st;
+      if ((st = plane<N, T>(c, buf, ks, nu)) != ACE_OK) return st;
       if ((st = launch(c, "pencil_accum_real", k_pencil_accum_real<N, T>,
                        dim3(xcd_pad((long)TILES * Bc)), dim3(64), 0, phi, ldphi,
                        (const cx<T>*)buf, W, ldW, i0, Ac, Am, j0, Bc, i0 > 0 ? 1 : 0)) != ACE_OK)
@@ -1264,22 +1250,20 @@ ace_status energy_direct_n(ace_ctx c, const GridInfo& g, const cx<T>* phi, int n
   const long total = (long)nocc * (nocc + 1) / 2;
   const size_t pair_bytes = (size_t)g.ng * sizeof(cx<T>);
   const long chunk = energy_chunk(c, g, sizeof(cx<T>), nocc);
-  const size_t kt_bytes = align_up((size_t)g.ng * sizeof(T), 256);
   const size_t part_bytes = align_up(((size_t)total * TILES + kSumBlocks) * sizeof(double), 256);
   ace_status st;
   if ((st = ws_begin(c, energy_direct_ws_bytes(c, g, sizeof(cx<T>), nocc))) != ACE_OK) return st;
-  T* Kt = (T*)ws_take(c, kt_bytes, &st);
   double* partial = (double*)ws_take(c, part_bytes, &st);
   cx<T>* buf = (cx<T>*)ws_take(c, (size_t)chunk * pair_bytes, &st);
-  if (!Kt || !partial || !buf) return st;
-  if ((st = make_kernel_table<T>(c, g, Kt, 1.0)) != ACE_OK) return st;
+  if (!partial || !buf) return st;
+  const ace_kspec ks = kspec_of(g, 1.0);
   for (long p0 = 0; p0 < total; p0 += chunk) {
     const int np = (int)std::min(chunk, total - p0);
     if ((st = fwd_slab<N, T>(c, phi, ldphi, phi, ldphi, buf, 1, 0, 1, 0, p0,
                              np)) != ACE_OK)
       return st;
     if ((st = launch(c, "pencil_energy", k_pencil_energy<N, T>, dim3(np * TILES), dim3(256), 0,
-                     (const cx<T>*)buf, (const T*)Kt, p0, partial)) != ACE_OK)
+                     (const cx<T>*)buf, ks, p0, partial)) != ACE_OK)
       return st;
   }
   double* blocks = partial + (size_t)total * TILES;

@@ -13,37 +13,59 @@
 namespace ace {
 namespace {
 
-constexpr double kFourPi = 12.566370614359172954;
-
-// Entry idx (< n^3) of the scaled kernel table.
+// Per-thread evaluator of the scaled kernel K'(G) (ace_kspec), in the
+// precision T of the pass: |G|^2 = sum_a (2 pi / L_a)^2 m_a^2 with m_a the
+// signed frequency of bin k_a (the Nyquist bin's sign does not matter:
+// squared).  The plane passes form the (k1, k2) part once per line and add the
+// k0 part per element, instead of reading an N_g table per pair.
 template <typename T>
-__device__ __forceinline__ void kernel_table_at(T* __restrict__ Kt, long idx, int n, double L0,
-                                                double L1, double L2, int kind, double mu,
-                                                double g0, double coef,
-                                                const double* __restrict__ dscale) {
-  const int k2 = (int)(idx % n);
-  const int k1 = (int)((idx / n) % n);
-  const int k0 = (int)(idx / ((long)n * n));
-  // integer frequency of FFT bin k (the Nyquist bin's sign does not matter: squared)
-  const int m0 = k0 <= n / 2 ? k0 : k0 - n;
-  const int m1 = k1 <= n / 2 ? k1 : k1 - n;
-  const int m2 = k2 <= n / 2 ? k2 : k2 - n;
-  const double twopi = 6.283185307179586477;
-  const double gx = twopi * m0 / L0, gy = twopi * m1 / L1, gz = twopi * m2 / L2;
-  const double g2 = gx * gx + gy * gy + gz * gz;
-  double K;
-  if (kind == kKindKinetic) {
-    K = 0.5 * g2;  // -1/2 Laplacian
-  } else if (g2 > 0.0) {
-    K = kFourPi / g2;
-    if (kind == ACE_ERFC) K *= -expm1(-g2 / (4.0 * mu * mu));
-  } else {
-    K = g0;
+struct KEval {
+  T t0, t1, t2, c, inv4mu2, g0c;
+  int n, kind;
+  __device__ __forceinline__ explicit KEval(const ace_kspec& ks)
+      : t0(T(ks.t2[0])), t1(T(ks.t2[1])), t2(T(ks.t2[2])),
+        c(T(ks.coef * (ks.dscale ? *ks.dscale : 1.0))), inv4mu2(T(ks.inv4mu2)),
+        g0c(T(ks.coef * (ks.dscale ? *ks.dscale : 1.0) * ks.g0)), n(ks.n), kind(ks.kind) {}
+  __device__ __forceinline__ T msq(int k) const {
+    const int m = k <= n / 2 ? k : k - n;
+    return T(m * m);
   }
-  // dscale (nullable): a further factor read from device memory (the upstream
-  // gradient of the energy in the backward pass), so no host round trip
-  Kt[idx] = T(coef * (dscale ? *dscale : 1.0) * K);
-}
+  // sum of the axis-1 and axis-2 terms of |G|^2.  The sums are explicit fused
+  // multiply-adds, so that every kernel (whatever the compiler would contract)
+  // rounds K' the same way: the forms of a pass must agree bit for bit.
+  __device__ __forceinline__ T part12(int k1, int k2) const {
+    return fma(t1, msq(k1), t2 * msq(k2));
+  }
+  // 1 - exp(-x) for x >= 0.  FP32: the hardware exp2 above x = 0.1 (relative
+  // error below 6e-7 there), the Taylor series to x^6 below (terms past it
+  // under 2e-9); FP64: expm1.
+  __device__ __forceinline__ static T one_minus_exp(T x) {
+    if constexpr (sizeof(T) == 4) {
+      const float e = __builtin_amdgcn_exp2f(-1.44269504088896341f * x);
+      float tay = fma(x, -1.0f / 720.0f, 1.0f / 120.0f);
+      tay = fma(x, tay, -1.0f / 24.0f);
+      tay = fma(x, tay, 1.0f / 6.0f);
+      tay = fma(x, tay, -0.5f);
+      tay = fma(x, tay, 1.0f);
+      return x > 0.1f ? 1.0f - e : x * tay;
+    } else {
+      return -expm1(-x);
+    }
+  }
+  __device__ __forceinline__ T at(int k0, T s12) const {
+    const T g2 = fma(t0, msq(k0), s12);
+    if (kind == kKindKinetic) return c * (T(0.5) * g2);
+    if (!(g2 > T(0))) return g0c;  // G = 0
+    // FP32: hardware reciprocal (1 ulp); FP64: correctly rounded division
+    T K;
+    if constexpr (sizeof(T) == 4)
+      K = c * (12.566370614359172954f * __builtin_amdgcn_rcpf(g2));
+    else
+      K = c * (T(12.566370614359172954) / g2);
+    if (kind == ACE_ERFC) K *= one_minus_exp(g2 * inv4mu2);
+    return K;
+  }
+};
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2:
 // physical workgroup b runs on XCD b % 8.  The launches pad the grid to a
@@ -212,7 +234,7 @@ __device__ __forceinline__ void slab_t1_body(cx<T>* s_all, int tid, bool dead, l
 template <int N, typename T, int P>
 __device__ __forceinline__ void plane_t1_body(cx<T>* s_all, int tid, bool dead, long lid0,
                                               long end, cx<T>* __restrict__ buf,
-                                              const T* __restrict__ Kt, int npairs) {
+                                              const ace_kspec& ks, int npairs) {
   constexpr int NN = N * N;
   constexpr int LD = N + 1;
   const int q = P == 1 ? 0 : tid / N;
@@ -230,10 +252,11 @@ __device__ __forceinline__ void plane_t1_body(cx<T>* s_all, int tid, bool dead, 
 #pragma unroll
     for (int r = 0; r < N; ++r) v[r] = plane[(size_t)r * NN + t];
     fft_line<N, -1, T>(v);
-    const T* kcol = Kt + (size_t)k1 * N + t;
+    const KEval<T> ke(ks);
+    const T s12 = ke.part12(k1, t);
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-      const T kk = kcol[(size_t)r * NN];
+      const T kk = ke.at(r, s12);
       v[r].x *= kk;
       v[r].y *= kk;
     }

@@ -1,8 +1,8 @@
 // Persistent form of the batched build (the W stage of Section 3, Eq. W, for
 // many independent instances): one launch per grid size runs the pass
 // launches of every instance of that size, recorded from the single-instance
-// build (kernel table, slab, plane and accumulate passes, chunk by chunk), as
-// tasks pulled from a queue in device memory.
+// build (slab, plane and accumulate passes, chunk by chunk), as tasks pulled
+// from a queue in device memory.
 //
 // Each workgroup loops: count its previous task as finished (after a release
 // fence), take the next task index from an atomic counter; if the task's
@@ -122,11 +122,6 @@ __global__ __launch_bounds__((PShape<N, T, AccQ>::kThreads)) void k_build_persis
     const ace_ptask tk = tasks[t];
     const ace_plaunch& l = L[tk.launch];
     switch (l.kind) {
-      case kPassTable:
-        for (long u = tk.u0 + tid; u < tk.u1; u += S::kThreads)
-          kernel_table_at<T>((T*)l.Kt, u, l.n, l.L0, l.L1, l.L2, l.table_kind, l.mu, l.g0, l.coef,
-                             nullptr);
-        break;
       case kPassSlab:
         for (long u = tk.u0; u < tk.u1; u += S::P) {
           slab_t1_body<N, T, S::P, S::kLoadBatch>(lds, tid, tid >= S::P * N, u, tk.u1,
@@ -138,8 +133,8 @@ __global__ __launch_bounds__((PShape<N, T, AccQ>::kThreads)) void k_build_persis
         break;
       case kPassPlane:
         for (long u = tk.u0; u < tk.u1; u += S::P) {
-          plane_t1_body<N, T, S::P>(lds, tid, tid >= S::P * N, u, tk.u1, (cx<T>*)l.buf,
-                                    (const T*)l.Kt, l.npairs);
+          plane_t1_body<N, T, S::P>(lds, tid, tid >= S::P * N, u, tk.u1, (cx<T>*)l.buf, l.ks,
+                                    l.npairs);
           __syncthreads();
         }
         break;
@@ -209,7 +204,7 @@ int persist_step(int n, size_t eb, int kind) {
   if (n == NV) {                                                                     \
     const int wv = eb == 16 ? PShape<NV, double, false>::WV : PShape<NV, float, false>::WV; \
     const int p = eb == 16 ? PShape<NV, double, false>::P : PShape<NV, float, false>::P;    \
-    return kind == kPassTable ? 64 * wv : (kind == kPassSlab || kind == kPassPlane) ? p : wv; \
+    return (kind == kPassSlab || kind == kPassPlane) ? p : wv;                             \
   }
   ACE_FOR_EACH_N(ACE_CASE)
 #undef ACE_CASE

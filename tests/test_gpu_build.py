@@ -29,6 +29,10 @@ def ace():
     (48, 20.5, 4, 6, "coulomb", 0.0, 0.0),
     (64, 27.0, 2, 3, "erfc", 0.3, 0.0),
     (72, 30.8, 2, 3, "erfc", 0.106, 0.0),
+    # strong screening: |G|^2 / (4 mu^2) below and across 0.1, where the FP32
+    # kernel switches from its series for 1 - exp(-x) to the hardware exp
+    (24, 12.0, 4, 6, "erfc", 2.5, 0.0),
+    (16, 6.0, 3, 5, "erfc", 1.2, 0.4),
 ])
 def test_build_W_matches_oracle(ace, prec, n, L, nocc, nband, kind, mu, g0):
     print(f"build_W prec={prec} n={n} nocc={nocc} nband={nband} kind={kind}", flush=True)
