@@ -378,7 +378,7 @@ __device__ __forceinline__ void chol_inv_body(const cx<double>* __restrict__ M, 
 // k_tri_inv: C = L^{-H}, one wave per column of L^{-1} (forward substitution,
 // many workgroups in parallel).  The fused single-workgroup form that also
 // carried the inverse in the Cholesky sweep measured 101 us at n = 80, the
-// two kernels 62 + 23 us.
+// two kernels 62 + 23 us (46 + 21 us with two columns per barrier).
 constexpr int kCholRegMax = 88;
 constexpr int kCholSlots = 4;  // ceil(88 * 89 / 2 / 1024)
 

@@ -318,7 +318,8 @@ __device__ __forceinline__ void accum_lds_body(cx<T>* acc, int t, long lid,
   // order (the circle method over the block's A bands, a bye when A is odd):
   // at step s band b meets partner p(s, b), and p(s, p(s, b)) = b, so the two
   // waves that need the spectrum of the pair {b, p} (one as u, one as conj u)
-  // read it at the same step, and the second read finds it in cache.
+  // read it at the same step.  (The L2 does not keep it between the two
+  // reads: a step's working set on one XCD exceeds it.)
   const bool tri = mode == 1 || (mode == 3 && b < A);
   const int rounds = A - 1 + (A & 1);  // players A (+1 bye when odd), fixed player m
   for (int s = 0; s < A; ++s) {
