@@ -104,7 +104,22 @@ typedef struct {
  * tune_cache (nullable): path of a tuning cache written by ace_autotune; the
  * settings it holds are loaded now (a file that does not exist yet is not an
  * error), and later ace_autotune calls with cache_path == NULL append their
- * results to it. */
+ * results to it.
+ * Environment, read here once per context:
+ *   ACE_TUNE_CACHE  path used as tune_cache when the argument is NULL;
+ *   ACE_TUNE        "0": library defaults only, tuned settings (loaded or made
+ *                   by ace_autotune) are kept but not used; "1": the first
+ *                   ace_build_W of a complex precision on a grid size and
+ *                   element size with no tuned setting runs ace_autotune on
+ *                   scratch orbitals of that call's sizes first (that call then
+ *                   allocates and synchronises; skipped under stream capture)
+ *                   and appends the result to the tuning cache; unset: tuned
+ *                   settings are used, none is made implicitly;
+ *   ACE_LOG         "1" or "stderr": one line per failed call (status and
+ *                   message), workspace growth, tuning results and context
+ *                   creation go to stderr; another value other than "0" names
+ *                   a file they are appended to.
+ * Fails with ACE_E_HIP when no HIP device is current. */
 ace_status ace_create(ace_ctx* out, void* hip_stream, const char* tune_cache);
 ace_status ace_destroy(ace_ctx ctx);
 /* Rebind the stream used by later calls.  All calls share the context's one
@@ -293,8 +308,10 @@ ace_status ace_rayleigh_ritz(ace_ctx ctx, const ace_grid* grid, ace_prec prec,
  * replays that graph without re-enqueueing and never synchronises; the data
  * behind the pointers may change between calls.  A call that captures anew
  * may wait for the context stream (when the workspace grows, and before the
- * task lists of the previous persistent graph are freed).  Pointers must not
- * overlap across instances' outputs; xi may not alias W here.
+ * task lists of the previous persistent graph are freed).  Instances run
+ * concurrently, so an instance's W or xi overlapping another instance's W,
+ * xi, phi or psi is an argument error (ACE_E_ARG, checked before anything is
+ * enqueued); inputs may be shared.  xi may not alias W here.
  */
 typedef struct {
   ace_grid grid;

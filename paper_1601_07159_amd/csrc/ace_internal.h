@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,12 @@ struct ace_ctx_s {
   int num_cus = 256;
   std::string last_error;
   std::string tune_cache;              // default cache file of ace_autotune ("" = none)
+  // ACE_TUNE at creation: -1 unset (tuned settings used, none made implicitly),
+  // 0 library defaults only (the tuned table is not consulted), 1 a complex
+  // build of a grid size with no tuned setting first runs the autotuner
+  int tune_mode = -1;
+  FILE* log = nullptr;                 // ACE_LOG target (stderr or an appended file)
+  bool log_owned = false;              // log was opened here (closed on destroy)
   hipEvent_t stream_event = nullptr;   // orders a new stream after the old one
   // profiling
   bool profiling = false;
@@ -130,6 +137,11 @@ bool stream_capturing(ace_ctx c);
 // Reads a tuning cache ("n eb budget jblock [shape]" per line) into the
 // context; a missing file returns false.
 bool tune_cache_read(ace_ctx c, const char* path);
+// The tuned setting for (grid size, element bytes), or null when there is none
+// or ACE_TUNE=0 switched tuned settings off.
+const ace_ctx_s::Tuned* tuned_for(ace_ctx c, int n, int eb);
+// Writes one line to the ACE_LOG target, if any (printf-style).
+void log_line(ace_ctx c, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 // Looks up, once per device and with that device current, the device address
 // of the allocation-free apply's static scratch array (noalloc.hip).
 void noalloc_setup(int device);

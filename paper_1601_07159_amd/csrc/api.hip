@@ -1,5 +1,7 @@
 // C ABI of libace: argument validation, workspace, dispatch to the kernels.
 #include <cmath>
+#include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
@@ -11,9 +13,30 @@
 
 namespace ace {
 
+void log_line(ace_ctx c, const char* fmt, ...) {
+  if (!c || !c->log) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[ace] ", c->log);
+  std::vfprintf(c->log, fmt, ap);
+  std::fputc('\n', c->log);
+  va_end(ap);
+  std::fflush(c->log);
+}
+
 ace_status fail(ace_ctx c, ace_status s, const std::string& msg) {
-  if (c) c->last_error = msg;
+  if (c) {
+    c->last_error = msg;
+    log_line(c, "%s: %s", ace_status_string(s), msg.c_str());
+  }
   return s;
+}
+
+const ace_ctx_s::Tuned* tuned_for(ace_ctx c, int n, int eb) {
+  if (c->tune_mode == 0) return nullptr;
+  for (const auto& t : c->tuned)
+    if (t.n == n && t.eb == eb) return &t;
+  return nullptr;
 }
 
 ace_status hip_fail(ace_ctx c, hipError_t e, const char* where) {
@@ -72,6 +95,7 @@ ace_status ws_begin(ace_ctx c, size_t total) {
   }
   c->ws = p;
   c->ws_bytes = total;
+  log_line(c, "workspace grown to %.1f MiB", total / 1048576.0);
   return ACE_OK;
 }
 
@@ -381,11 +405,34 @@ ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream, const char* tune_ca
   ace_ctx c = new (std::nothrow) ace_ctx_s();
   if (!c) return ACE_E_NOMEM;
   c->stream = (hipStream_t)stream;
+  // ACE_LOG: "1" or "stderr" logs to stderr, another non-empty value other
+  // than "0" names a file the log is appended to
+  if (const char* lg = std::getenv("ACE_LOG")) {
+    if (!std::strcmp(lg, "1") || !std::strcmp(lg, "stderr")) {
+      c->log = stderr;
+    } else if (*lg && std::strcmp(lg, "0")) {
+      c->log = std::fopen(lg, "a");
+      c->log_owned = c->log != nullptr;
+    }
+  }
+  if (const char* tm = std::getenv("ACE_TUNE")) {
+    if (!std::strcmp(tm, "0")) c->tune_mode = 0;
+    else if (!std::strcmp(tm, "1")) c->tune_mode = 1;
+  }
+  // ACE_TUNE_CACHE names the tuning cache when the caller passes none
+  if (!tune_cache) {
+    const char* env = std::getenv("ACE_TUNE_CACHE");
+    if (env && *env) tune_cache = env;
+  }
   if (tune_cache) {
     c->tune_cache = tune_cache;
-    (void)tune_cache_read(c, tune_cache);  // a cache not written yet is not an error
+    // a cache not written yet is not an error
+    const bool found = tune_cache_read(c, tune_cache);
+    log_line(c, "tuning cache %s: %s, %zu settings", tune_cache, found ? "read" : "not found",
+             c->tuned.size());
   }
   if (hipGetDevice(&c->device) != hipSuccess) {
+    if (c->log_owned) std::fclose(c->log);
     delete c;
     return ACE_E_HIP;
   }
@@ -395,6 +442,8 @@ ACE_EXPORT ace_status ace_create(ace_ctx* out, void* stream, const char* tune_ca
       cus > 0)
     c->num_cus = cus;
   noalloc_setup(c->device);  // device address of the allocation-free apply's scratch
+  log_line(c, "context on device %d (%d CUs), stream %p, ACE_TUNE mode %d", c->device,
+           c->num_cus, stream, c->tune_mode);
   *out = c;
   return ACE_OK;
 }
@@ -421,6 +470,7 @@ ACE_EXPORT ace_status ace_destroy(ace_ctx c) {
     hipEventDestroy(p.e1);
   }
   for (auto e : c->free_events) hipEventDestroy(e);
+  if (c->log_owned) std::fclose(c->log);
   delete c;
   return ACE_OK;
 }
@@ -552,6 +602,27 @@ ACE_EXPORT ace_status ace_build_W(ace_ctx c, const ace_grid* grid, ace_prec prec
   if (overlap(sw, span_of(phi, n_occ, ld_phi, g.ng, eb)) ||
       overlap(sw, span_of(psi, n_band, ld_psi, g.ng, eb)))
     return fail(c, ACE_E_ARG, "W overlaps an input");
+  if (c->tune_mode == 1 && (prec == ACE_FP64 || prec == ACE_FP32 || prec == ACE_MIXED) &&
+      !tuned_for(c, g.n, (int)eb) && !stream_capturing(c)) {
+    // ACE_TUNE=1: tune this grid size and element size once, on scratch
+    // orbitals of this call's sizes (allocates and synchronises); a failed
+    // tuning run is logged and the defaults are kept for this size
+    long bb = 0, bj = 0;
+    int bs = 0, ba = 0;
+    double ms = 0.0;
+    const ace_status ts = ace_autotune(c, grid, prec, n_occ, n_band, nullptr, &bb, &bj, &bs,
+                                       &ba, &ms);
+    if (ts == ACE_OK) {
+      log_line(c, "tuned n=%d elem_bytes=%zu: budget %ld, band block %ld, shape %d, accum %d "
+               "(%.3f ms per build)", g.n, eb, bb, bj, bs, ba, ms);
+    } else {
+      log_line(c, "tuning n=%d elem_bytes=%zu failed (%s); defaults kept", g.n, eb,
+               ace_status_string(ts));
+      c->tuned.push_back({g.n, (int)eb, 0, 0, 0, 0});
+      ++c->tune_gen;
+      c->last_error.clear();
+    }
+  }
   if (prec == ACE_REAL64)
     return build_W_real_impl<double>(c, g, (const double*)phi, n_occ, ld_phi, (const double*)psi,
                                      n_band, ld_psi, (double*)W, ld_W, scale);

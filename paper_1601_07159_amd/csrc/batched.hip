@@ -494,6 +494,34 @@ ACE_EXPORT ace_status ace_build_W_batched(ace_ctx c, int n_inst, const ace_insta
     plan[k].bytes = std::max(bp.bytes, in.xi ? compress_ws_bytes(in.n_band, g.ng) : (size_t)0);
     plan[k].cost = (double)in.n_occ * in.n_band * (double)g.ng;
   }
+  // Instances run concurrently: no instance's output may overlap another
+  // instance's inputs or outputs.
+  auto outs = [&](int k, Span* o) {
+    const ace_instance& in = inst[k];
+    const size_t eb = elem_bytes((ace_prec)in.prec);
+    o[0] = span_of(in.W, in.n_band, in.ld_W, plan[k].g.ng, eb);
+    o[1] = in.xi ? span_of(in.xi, in.n_band, in.ld_xi, plan[k].g.ng, eb) : Span{};
+  };
+  for (int k = 0; k < n_inst; ++k) {
+    Span ok[2];
+    outs(k, ok);
+    for (int m = 0; m < n_inst; ++m) {
+      if (m == k) continue;
+      const ace_instance& im = inst[m];
+      const size_t eb = elem_bytes((ace_prec)im.prec);
+      Span om[4];
+      outs(m, om);
+      om[2] = span_of(im.phi, im.n_occ, im.ld_phi, plan[m].g.ng, eb);
+      om[3] = span_of(im.psi, im.n_band, im.ld_psi, plan[m].g.ng, eb);
+      for (const Span& a : ok)
+        for (const Span& b : om)
+          if (overlap(a, b)) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "an output of instance %d overlaps instance %d", k, m);
+            return fail(c, ACE_E_ARG, buf);
+          }
+    }
+  }
   const int form = c->batch_form ? c->batch_form : kDefaultBatchForm;
   return form == 2 ? batched_persistent(c, n_inst, inst, plan)
                    : batched_launches(c, n_inst, inst, plan);

@@ -836,11 +836,10 @@ BuildPlan plan_build(ace_ctx c, const GridInfo& g, size_t eb, int nocc, int nban
   // explicit knobs first, then an autotuned entry for this grid size, then defaults
   size_t budget = c->pair_budget;
   long jblock = c->jblock;
-  for (const auto& t : c->tuned)
-    if (t.n == g.n && t.eb == (int)eb) {
-      if (!budget) budget = (size_t)t.budget;
-      if (!jblock) jblock = t.jblock;
-    }
+  if (const auto* t = tuned_for(c, g.n, (int)eb)) {
+    if (!budget) budget = (size_t)t->budget;
+    if (!jblock) jblock = t->jblock;
+  }
   if (!budget) budget = default_pair_budget();
   if (c->budget_cap && budget > c->budget_cap) budget = c->budget_cap;
   long maxpairs = (long)(budget / pair_bytes);
@@ -964,9 +963,8 @@ ace_kspec kspec_of(const GridInfo& g, double coef, const double* dscale = nullpt
 // this grid size and element size.
 int line_shape(ace_ctx c, int n, int eb) {
   if (c->fft_shape) return c->fft_shape;
-  for (const auto& t : c->tuned)
-    if (t.n == n && t.eb == eb && t.shape) return t.shape;
-  return 0;
+  const auto* t = tuned_for(c, n, eb);
+  return t ? t->shape : 0;
 }
 
 template <int N, typename T>
@@ -1065,8 +1063,8 @@ ace_status plane(ace_ctx c, cx<T>* buf, const ace_kspec& ks, int np) {
 template <int N, typename T>
 int accum_form(ace_ctx c) {
   if (c->accum_shape) return c->accum_shape;
-  for (const auto& t : c->tuned)
-    if (t.n == N && t.eb == (int)sizeof(cx<T>) && t.accum) return t.accum;
+  const auto* t = tuned_for(c, N, (int)sizeof(cx<T>));
+  if (t && t->accum) return t->accum;
   return N <= 64 ? 16 : 1;
 }
 

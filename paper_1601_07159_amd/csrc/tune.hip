@@ -5,7 +5,11 @@
 // a quad or an octet of lanes per line; the tile of a line FFT); keeps the
 // fastest in the context, and optionally appends it to a text cache file
 // ("n elem_bytes budget jblock shape" per line) that ace_tune_load reads back.
+#include <cerrno>
+#include <cstdint>
 #include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "ace_internal.h"
@@ -188,25 +192,50 @@ ACE_EXPORT ace_status ace_autotune(ace_ctx c, const ace_grid* grid, ace_prec pre
 }
 
 namespace ace {
+// One whole line of f into out (without the newline); false at end of file.
+static bool read_line(FILE* f, std::string& out) {
+  out.clear();
+  int ch;
+  while ((ch = std::fgetc(f)) != EOF && ch != '\n') out.push_back((char)ch);
+  return ch != EOF || !out.empty();
+}
+
+// Parses up to 6 integers separated by blanks; returns how many, or -1 when the
+// line holds anything else (a value out of range of long included).
+static int parse_fields(const std::string& line, long* v) {
+  const char* p = line.c_str();
+  int got = 0;
+  while (true) {
+    while (*p == ' ' || *p == '\t' || *p == '\r') ++p;
+    if (!*p) return got;
+    if (got == 6) return -1;
+    char* end = nullptr;
+    errno = 0;
+    const long x = std::strtol(p, &end, 10);
+    if (end == p || errno == ERANGE) return -1;
+    if (*end && *end != ' ' && *end != '\t' && *end != '\r') return -1;
+    v[got++] = x;
+    p = end;
+  }
+}
+
 bool tune_cache_read(ace_ctx c, const char* cache_path) {
-  FILE* f = fopen(cache_path, "r");
+  FILE* f = std::fopen(cache_path, "r");
   if (!f) return false;
-  // one setting per line: "n eb budget jblock [shape]" (shape 0 when absent)
-  char line[256];
-  while (fgets(line, sizeof line, f)) {
-    int n, eb, shape = 0;
-    long bud, jb;
-    int accum = 0;
-    const int got = sscanf(line, "%d %d %ld %ld %d %d", &n, &eb, &bud, &jb, &shape, &accum);
+  // one setting per line: "n eb budget jblock [shape [accum]]" (0 when absent);
+  // lines that do not parse or hold values out of range are skipped
+  std::string line;
+  while (read_line(f, line)) {
+    long v[6] = {0, 0, 0, 0, 0, 0};
+    const int got = parse_fields(line, v);
     if (got < 4) continue;
-    if (got == 4) shape = 0;
-    if (got <= 5) accum = 0;
-    if (n > 0 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0 &&
+    const long n = v[0], eb = v[1], bud = v[2], jb = v[3], shape = v[4], accum = v[5];
+    if (n > 0 && n <= 4096 && (eb == 8 || eb == 16) && bud >= 0 && jb >= 0 && jb <= INT32_MAX &&
         (shape == 0 || shape == 1 || shape == 4 || shape == 8 || shape == 16) &&
         (accum == 0 || accum == 1 || accum == 16))
-      upsert(c, n, eb, bud, jb, shape, accum);
+      upsert(c, (int)n, (int)eb, bud, jb, (int)shape, (int)accum);
   }
-  fclose(f);
+  std::fclose(f);
   return true;
 }
 }  // namespace ace

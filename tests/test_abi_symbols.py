@@ -56,3 +56,32 @@ def test_null_context_is_an_argument_error(lib):
     assert lib.ace_apply(None, ctypes.byref(g), 0, None, 1, 1, None, 1, 1, None, 1) == 1
     assert lib.ace_destroy(None) == 1
     assert lib.ace_create(None, None, None) == 1
+
+
+def test_environment_read_at_create(tmp_path):
+    """ace_create reads ACE_LOG and ACE_TUNE_CACHE before it looks for a
+    device: the log names the cache and the settings it held.  Without a GPU the
+    call then fails with ACE_E_HIP; with one it succeeds."""
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    cache.write_text("16 8 0 0 8\n24 16 268435456 0 4 1\nnot a setting\n")
+    log = tmp_path / "ace.log"
+    code = (
+        "import ctypes\n"
+        "from paper_1601_07159_amd import _lib\n"
+        "lib = _lib.load()\n"
+        "c = ctypes.c_void_p()\n"
+        "st = lib.ace_create(ctypes.byref(c), None, None)\n"
+        "assert st in (0, 4), st\n"
+        "if st == 0:\n"
+        "    lib.ace_destroy(c)\n"
+    )
+    env = dict(os.environ, ACE_LOG=str(log), ACE_TUNE_CACHE=str(cache), ACE_TUNE="0",
+               PYTHONPATH=ROOT)
+    subprocess.run([sys.executable, "-c", code], env=env, check=True, cwd=ROOT, timeout=120)
+    text = log.read_text()
+    assert f"tuning cache {cache}: read, 2 settings" in text
+    env["ACE_TUNE_CACHE"] = str(tmp_path / "absent.txt")
+    subprocess.run([sys.executable, "-c", code], env=env, check=True, cwd=ROOT, timeout=120)
+    assert "absent.txt: not found, 0 settings" in log.read_text()

@@ -54,3 +54,55 @@ def test_tune_load_reads_lines_without_shape(tmp_path):
     W = to_np(ctx.build_W(x[:nocc], x, ggrid(n, L), "fp32"))
     ctx.close()
     assert rel(W.reshape(ref.shape), ref) <= tol("fp32")
+
+
+def test_environment_tune_on_first_build(tmp_path, monkeypatch):
+    """ACE_TUNE=1: the first build of a grid size runs the tuner once and
+    appends its choice to the ACE_TUNE_CACHE file; ACE_LOG records it; the
+    builds match the oracle."""
+    from paper_1601_07159_amd import ace
+    n, L, nocc, nband = 16, 7.0, 4, 7
+    print(f"env tune n={n}", flush=True)
+    cache, log = tmp_path / "tune.txt", tmp_path / "ace.log"
+    monkeypatch.setenv("ACE_TUNE", "1")
+    monkeypatch.setenv("ACE_TUNE_CACHE", str(cache))
+    monkeypatch.setenv("ACE_LOG", str(log))
+    psi = synth.smooth_orbitals(n, L, nband, seed=45)
+    ref = O.build_W(psi[:nocc], psi, ogrid(n, L))
+    x = to_gpu(psi, "fp32")
+    ctx = ace.Context()
+    W1 = to_np(ctx.build_W(x[:nocc], x, ggrid(n, L), "fp32"))
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[:2] == [str(n), "8"]
+    W2 = to_np(ctx.build_W(x[:nocc], x, ggrid(n, L), "fp32"))
+    assert len(cache.read_text().splitlines()) == 1      # tuned once
+    with pytest.raises(ace.AceError):
+        ctx.build_W(x[:nocc], x, ggrid(n, L), "fp32", scale=float("nan"))
+    ctx.close()
+    text = log.read_text()
+    assert f"tuned n={n} elem_bytes=8" in text
+    assert "scale must be finite" in text
+    assert np.array_equal(W1, W2)
+    assert rel(W1.reshape(ref.shape), ref) <= tol("fp32")
+
+
+def test_environment_tune_off_uses_defaults(tmp_path, monkeypatch):
+    """ACE_TUNE=0: a loaded setting (here the octet line shape, which rounds
+    differently from the default shape) is not used."""
+    import torch
+    from paper_1601_07159_amd import ace
+    n, L, nocc, nband = 16, 6.5, 5, 8
+    psi = to_gpu(synth.smooth_orbitals(n, L, nband, seed=71), "fp32").reshape(nband, -1)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"{n} 8 0 0 8\n")
+    g = ggrid(n, L)
+    c_def = ace.Context()
+    c_on = ace.Context(0, tune_cache=str(cache))
+    monkeypatch.setenv("ACE_TUNE", "0")
+    c_off = ace.Context(0, tune_cache=str(cache))
+    Wd, Won, Woff = (c.build_W(psi[:nocc], psi, g, "fp32") for c in (c_def, c_on, c_off))
+    torch.cuda.synchronize()
+    assert torch.equal(Woff, Wd)
+    assert not torch.equal(Won, Wd)
+    for c in (c_def, c_on, c_off):
+        c.close()
