@@ -389,10 +389,12 @@ __device__ __forceinline__ cx<T> quad_swap(cx<T> a) {
 template <int D>
 __device__ __forceinline__ unsigned lane_xor_u32(unsigned u) {
   static_assert(D == 1 || D == 2 || D == 16 || D == 32, "lane distance");
+  // (a quad permutation has a valid source for every lane, so the DPP move
+  // needs no old value: mov_dpp leaves it undefined and saves a register copy)
   if constexpr (D == 1) {
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, kQuadXor1, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)u, kQuadXor1, 0xF, 0xF, false);
   } else if constexpr (D == 2) {
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)u, kQuadXor2, 0xF, 0xF, false);
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)u, kQuadXor2, 0xF, 0xF, false);
   } else {
     const bool upper = (__lane_id() & D) != 0;
     if constexpr (D == 16) {
@@ -420,19 +422,85 @@ __device__ __forceinline__ cx<T> lane_xor(cx<T> a) {
   return {lane_xor<D>(a.x), lane_xor<D>(a.y)};
 }
 
+// Quad twiddles exp(S 2 pi i h k / N) (h = 0..3, k = 0..M-1, M = N / 4) in
+// the working precision, stored [k][h] so that lane h reads entry (k, h) at a
+// fixed per-lane base plus the compile-time offset 4 k: one load per value
+// instead of choosing among four constants by lane.  Entries equal
+// root<N, S, T>(h k) (h k < N), with exp(0) stored as 1 + 0i.
+template <int N, typename T>
+struct QuadRoots {
+  cx<T> w[2][N];  // [0]: S = -1, [1]: S = +1
+  constexpr QuadRoots() : w() {
+    for (int k = 0; k < N / 4; ++k)
+      for (int h = 0; h < 4; ++h) {
+        const cs_pair p = ce_unit_root((long)h * k, N);
+        const bool one = h * k == 0;
+        w[0][4 * k + h] = one ? cx<T>{T(1), T(0)} : cx<T>{T(p.c), T(-1 * p.s)};
+        w[1][4 * k + h] = one ? cx<T>{T(1), T(0)} : cx<T>{T(p.c), T(p.s)};
+      }
+  }
+};
+
+template <int N, typename T>
+__constant__ constexpr QuadRoots<N, T> kQuadRoots{};
+
+// Butterfly across lanes l and l ^ D: partner + sg * own, sg = +1 on the lane
+// without bit D and -1 on the lane with it, i.e. (u + w, u - w) for u, w
+// held by the lower and upper lane.  D = 1, 2: a DPP quad permutation brings
+// the partner's value.  D = 16, 32: the permlane swap returns both halves in
+// every lane ([0] the lower lane's value, [1] the upper's), so no per-lane
+// choice is needed; r0 + sg r1 rounds exactly as partner + sg own.
+template <int D>
+__device__ __forceinline__ float xor_bfly(float own, float sg) {
+  if constexpr (D == 1 || D == 2) {
+    return fma(sg, own, lane_xor<D>(own));
+  } else {
+    static_assert(D == 16 || D == 32, "lane distance");
+    const unsigned u = __builtin_bit_cast(unsigned, own);
+    const auto r = D == 16 ? __builtin_amdgcn_permlane16_swap(u, u, false, false)
+                           : __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return fma(sg, __builtin_bit_cast(float, (unsigned)r[1]),
+               __builtin_bit_cast(float, (unsigned)r[0]));
+  }
+}
+template <int D>
+__device__ __forceinline__ double xor_bfly(double own, double sg) {
+  if constexpr (D == 1 || D == 2) {
+    return fma(sg, own, lane_xor<D>(own));
+  } else {
+    static_assert(D == 16 || D == 32, "lane distance");
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, own);
+    const unsigned lo = (unsigned)(u & 0xffffffffULL), hi = (unsigned)(u >> 32);
+    const auto rl = D == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                            : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = D == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                            : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double r0 = __builtin_bit_cast(
+        double, ((unsigned long long)(unsigned)rh[0] << 32) | (unsigned long long)(unsigned)rl[0]);
+    const double r1 = __builtin_bit_cast(
+        double, ((unsigned long long)(unsigned)rh[1] << 32) | (unsigned long long)(unsigned)rl[1]);
+    return fma(sg, r1, r0);
+  }
+}
+template <int D, typename T>
+__device__ __forceinline__ cx<T> xor_bfly(cx<T> own, T sg) {
+  return {xor_bfly<D>(own.x, sg), xor_bfly<D>(own.y, sg)};
+}
+
 template <int N, int S, typename T>
 __device__ __forceinline__ void quad_twiddle(cx<T>* v, int h) {
   constexpr int M = N / 4;
+  const cx<T>* tw = kQuadRoots<N, T>.w[S > 0 ? 1 : 0] + h;
 #pragma unroll
-  for (int k = 1; k < M; ++k) {
-    const cx<T> w1 = root<N, S, T>(k % N);
-    const cx<T> w2 = root<N, S, T>((2 * k) % N);
-    const cx<T> w3 = root<N, S, T>((3 * k) % N);
-    const cx<T> w = h == 0 ? cx<T>{T(1), T(0)} : h == 1 ? w1 : h == 2 ? w2 : w3;
-    v[k] = cmul(v[k], w);
-  }
+  for (int k = 1; k < M; ++k) v[k] = cmul(v[k], tw[4 * k]);
 }
 
+// The two radix-2 exchanges of the 4-point DFT across a quad, written without
+// choosing operands by lane: with sigma = +-1 per lane, p + sigma v is exactly
+// the rounded p - v or v + p of the butterfly, and the factor (S i) of the
+// second stage is applied before the exchange by the lane whose value it
+// multiplies (a product by +-i is exact), so every lane ends with
+// received + sigma * own.
 // D1: lane distance between the parts h and h ^ 1 of a line (1: the 4 lanes
 // of a quad; 16: lanes l, l + 16, l + 32, l + 48, so that 16 consecutive
 // lanes hold the same part of 16 lines, which keeps their global accesses
@@ -444,19 +512,14 @@ __device__ __forceinline__ void fft_quad_d2b(cx<T>* v, int h) {
   fft_line<M, S, T>(v);
   quad_twiddle<N, S, T>(v, h);
   const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
+  const T sg_hi = hi ? T(-1) : T(1), sg_odd = odd ? T(-1) : T(1);
+  const bool rot = hi && odd;
 #pragma unroll
-  for (int k = 0; k < M; ++k) {  // lanes h, h^2: (u, w) -> (u + w, u - w)
-    const cx<T> p = lane_xor<2 * D1>(v[k]);
-    v[k] = hi ? csub(p, v[k]) : cadd(v[k], p);
-  }
+  for (int k = 0; k < M; ++k)  // lanes h, h^2: (u, w) -> (u + w, u - w)
+    v[k] = xor_bfly<2 * D1>(v[k], sg_hi);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {  // lanes h, h^1: (u, w) -> (u + t w, u - t w), t = (S i)^(h >> 1)
-    const cx<T> p = lane_xor<D1>(v[k]);
-    const cx<T> q = odd ? v[k] : p;
-    const cx<T> r = odd ? p : v[k];
-    const cx<T> tq = hi ? mul_si<S>(q) : q;
-    v[k] = odd ? csub(r, tq) : cadd(r, tq);
-  }
+  for (int k = 0; k < M; ++k)  // lanes h, h^1: (u, w) -> (u + t w, u - t w), t = (S i)^(h >> 1)
+    v[k] = xor_bfly<D1>(rot ? mul_si<S>(v[k]) : v[k], sg_odd);  // the odd lane's w enters as t w
 }
 
 template <int N, int S, typename T, int D1 = 1>
@@ -464,19 +527,14 @@ __device__ __forceinline__ void fft_quad_b2d(cx<T>* v, int h) {
   constexpr int M = N / 4;
   static_assert(N % 4 == 0, "quad lines need N divisible by 4");
   const bool hi = (h >> 1) != 0, odd = (h & 1) != 0;
+  const T sg_hi = hi ? T(-1) : T(1), sg_odd = odd ? T(-1) : T(1);
+  const bool rot = hi && odd;
 #pragma unroll
-  for (int k = 0; k < M; ++k) {  // lanes L, L^1 hold X[c], X[c + 2]: sum and difference
-    const cx<T> p = lane_xor<D1>(v[k]);
-    v[k] = odd ? csub(p, v[k]) : cadd(v[k], p);
-  }
+  for (int k = 0; k < M; ++k)  // lanes L, L^1 hold X[c], X[c + 2]: sum and difference
+    v[k] = xor_bfly<D1>(v[k], sg_odd);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {  // lanes L, L^2: the odd pair carries the factor S i
-    const cx<T> p = lane_xor<2 * D1>(v[k]);
-    const cx<T> q = hi ? v[k] : p;
-    const cx<T> r = hi ? p : v[k];
-    const cx<T> wq = odd ? mul_si<S>(q) : q;
-    v[k] = hi ? csub(r, wq) : cadd(r, wq);
-  }
+  for (int k = 0; k < M; ++k)  // lanes L, L^2: the odd pair carries the factor S i
+    v[k] = xor_bfly<2 * D1>(rot ? mul_si<S>(v[k]) : v[k], sg_hi);  // the upper lane's q enters as w q
   quad_twiddle<N, S, T>(v, h);
   fft_line<M, S, T>(v);
 }

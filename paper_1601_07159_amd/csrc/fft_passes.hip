@@ -97,7 +97,8 @@ __global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict
   const int t = threadIdx.x;
   const int l = t >> 2, h = t & 3;
   const int rr = t / N, cc = t - rr * N;  // element t + 4N q sits at row 4q + rr, column cc
-  {
+  cx<T> v[M];
+  if constexpr (kQuadStage<N>) {
     cx<T> va[M], vb[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) va[q] = a[(4 * q + rr) * N + cc];
@@ -105,12 +106,23 @@ __global__ __launch_bounds__(4 * N) void k_pair_fwd_slab(const cx<T>* __restrict
     for (int q = 0; q < M; ++q) vb[q] = b[(4 * q + rr) * N + cc];
 #pragma unroll
     for (int q = 0; q < M; ++q) s[(4 * q + rr) * LD + cc] = cmulc(va[q], vb[q]);
-  }
-  __syncthreads();
-  cx<T> v[M];
-  // axis 2: row l
+    __syncthreads();
+    // axis 2: row l
 #pragma unroll
-  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
+    for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
+  } else {
+    // row l of the pair product straight from global memory, decimated over
+    // the quad (each 16 lanes read 4 rows x 32 contiguous bytes; the rest of
+    // those lines are read by the next loads): no LDS pass and no barrier
+    // before the row transform
+    cx<T> va[M], vb[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) va[m] = a[l * N + h + 4 * m];
+#pragma unroll
+    for (int m = 0; m < M; ++m) vb[m] = b[l * N + h + 4 * m];
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = cmulc(va[m], vb[m]);
+  }
   fft_quad_d2b<N, -1, T>(v, h);
 #pragma unroll
   for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
@@ -154,8 +166,10 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
   __shared__ cx<T> s[N * LD];
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
   if (lid >= (long)N * npairs) return;
-  const int k1 = (int)(lid / npairs);
-  const int p = (int)(lid - (long)k1 * npairs);
+  // planes of one pair on neighbouring workgroups: at every k0 their rows
+  // form one contiguous N^2 run of the spectrum (the pairs share no input)
+  const int p = (int)(lid / N);
+  const int k1 = (int)(lid - (long)p * N);
   const int t = threadIdx.x;
   const int l = t >> 2, h = t & 3;
   cx<T>* plane = buf + (size_t)p * N * NN + (size_t)k1 * N;
@@ -195,15 +209,28 @@ __global__ __launch_bounds__(4 * N) void k_plane_kernel(cx<T>* __restrict__ buf,
 #pragma unroll
   for (int m = 0; m < M; ++m) s[(h + 4 * m) * LD + l] = v[m];
   __syncthreads();
+  if constexpr (kQuadStage<N>) {
 #pragma unroll
-  for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
-  fft_quad_d2b<N, +1, T>(v, h);
-  // row l is read and rewritten by its own quad only (one wave, in order)
+    for (int m = 0; m < M; ++m) v[m] = s[l * LD + h + 4 * m];
+    fft_quad_d2b<N, +1, T>(v, h);
+    // row l is read and rewritten by its own quad only (one wave, in order)
 #pragma unroll
-  for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
-  __syncthreads();
+    for (int k = 0; k < M; ++k) s[l * LD + quad_block_index(k, M, h)] = v[k];
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
+    for (int q = 0; q < M; ++q) plane[(size_t)(4 * q + rr) * NN + cc] = s[(4 * q + rr) * LD + cc];
+  } else {
+    // row l read in block layout, transformed to the decimated one, and
+    // stored straight from registers (each 16 lanes write 4 rows x 32
+    // contiguous bytes; a wave's 18 stores complete its 16 rows): no second
+    // LDS pass and no barrier
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = s[l * LD + quad_block_index(k, M, h)];
+    fft_quad_b2d<N, +1, T>(v, h);
+    cx<T>* row = plane + (size_t)l * NN + h;
+#pragma unroll
+    for (int m = 0; m < M; ++m) row[4 * m] = v[m];
+  }
 }
 
 // Split-line forms of the slab and plane passes: every line FFT is split over
@@ -290,8 +317,8 @@ __global__ __launch_bounds__(64 * kRowWaves<N>) void k_plane_kernel_row(cx<T>* _
   __shared__ cx<T> s[N * LD];
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
   if (lid >= (long)N * npairs) return;
-  const int k1 = (int)(lid / npairs);
-  const int p = (int)(lid - (long)k1 * npairs);
+  const int p = (int)(lid / N);  // pair-major, as in the quad plane pass
+  const int k1 = (int)(lid - (long)p * N);
   const int t = threadIdx.x;
   const int h = (t >> 4) & 3;
   const int l = ((t >> 6) << 4) + (t & 15);
@@ -402,8 +429,8 @@ __global__ __launch_bounds__(8 * N) void k_plane_kernel_oct(cx<T>* __restrict__ 
   __shared__ cx<T> s[N * LD];
   const long lid = xcd_logical(blockIdx.x, gridDim.x);
   if (lid >= (long)N * npairs) return;
-  const int k1 = (int)(lid / npairs);
-  const int p = (int)(lid - (long)k1 * npairs);
+  const int p = (int)(lid / N);  // pair-major, as in the quad plane pass
+  const int k1 = (int)(lid - (long)p * N);
   const int t = threadIdx.x;
   const int l = t >> 3, h = t & 7;
   const OctTw<N, T> tw = oct_twiddles<N, T>(h);
