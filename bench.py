@@ -193,6 +193,10 @@ def main():
                     help="cfg4: skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (for counter scaling)")
+    ap.add_argument("--no-others", action="store_true",
+                    help="the default cfg2 run with its CPU baseline also times cfg2r, cfg3, "
+                         "cfg4 and cfg5 for a few steps each (child processes, after the timed "
+                         "region) and reports them under extra.other_workloads; this skips them")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -457,8 +461,45 @@ def main():
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
         out["cpu_baseline"] = with_ratios(cpu_baseline(cfg), value)
+    if args.workload == "cfg2" and not args.no_cpu and not args.no_others:
+        extra["other_workloads"] = other_workloads(args)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def other_workloads(args):
+    """The other configurations, a few timed steps each, as child processes of
+    this run (so that one bench invocation times every workload): the summary
+    of each one's JSON line."""
+    import subprocess
+    res = {}
+    steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    for w in ("cfg2r", "cfg3", "cfg4", "cfg5"):
+        log(f"bench: other workload {w} ({steps} steps)")
+        cmd = [sys.executable, os.path.abspath(__file__), "--workload", w, "--steps", str(steps),
+               "--warmup", str(warmup), "--no-cpu", "--no-others"]
+        try:
+            r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+            line = [x for x in r.stdout.strip().splitlines() if x.startswith("{")]
+            if r.returncode != 0 or not line:
+                res[w] = {"error": f"exit {r.returncode}: {r.stderr.strip()[-300:]}"}
+                continue
+            d = json.loads(line[-1])
+        except (subprocess.TimeoutExpired, json.JSONDecodeError) as e:
+            res[w] = {"error": repr(e)[:300]}
+            continue
+        e = d.get("extra", {})
+        rf = d.get("roofline") or {}
+        res[w] = {k: v for k, v in {
+            "config": d["config"].get("workload"), "metric": d["metric"], "value": d["value"],
+            "unit": d["unit"], "ms_per_step": d["ms_per_step"], "steps": d["steps"],
+            "dtype": d["dtype"],
+            "roofline": {k2: rf.get(k2) for k2 in ("kernel", "bound", "achieved", "peak", "unit",
+                                                   "frac", "traffic")},
+            "errors_vs_fp64": e.get("errors_vs_fp64"), "errors_vs_oracle": e.get("errors_vs_oracle"),
+            "forms": e.get("forms"), "stage_ms": e.get("stage_ms"),
+        }.items() if v is not None}
+    return res
 
 
 def with_ratios(cpu, gpu_value):
