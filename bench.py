@@ -694,6 +694,8 @@ def run_autograd(args, cfg):
         dev, torch.complex64).reshape(nocc, -1)
     phi = phi0.clone().requires_grad_(True)
     ctx = ace.context(0)
+    if args.fft_shape:
+        ctx.set_tuning("fft_shape", args.fft_shape)
 
     def step():
         phi.grad = None
