@@ -1,6 +1,6 @@
 """Writes the stored expected values under tests/golden/ from the FP64 oracle.
 
-Run from the repository root:  python tests/golden/make_golden.py [small|full72|full64 ...]
+Run from the repository root:  python tests/golden/make_golden.py [small|full48|full64|full72 ...]
 (no argument: all).  Only the oracle and the seeded input generator are called;
 the full-size cases split the oracle's W over columns j across worker
 processes (each worker calls the oracle's build_W for its own columns).
@@ -131,6 +131,65 @@ def full72(workers):
         f.write("\n")
 
 
+N48, L48, NB48, NOCC48 = 48, 20.5, 80, 64
+
+
+def _w_columns48(cols):
+    """Worker: columns j of W = V_X[phi] psi at 48^3 (oracle)."""
+    psi = _shared["psi48"]
+    return cols, O.build_W(psi[:NOCC48], psi, O.Grid.cubic(N48, L48), columns=cols)
+
+
+def full48(workers, real=False):
+    """48^3, L = 20.5 bohr, 80 smooth orbitals (seed 0; complex, or real ones
+    from the real-orbital generator), N_occ = 64, Coulomb kernel with g0 = 0:
+    the whole W from the oracle, then M, L, xi and the values the full-size
+    test compares.  For real orbitals the oracle's complex arithmetic gives a
+    W whose imaginary part is rounding only (checked below 1e-12 of its norm);
+    the stored values are of the real part."""
+    t0 = time.time()
+    psi = (synth.real_orbitals(N48, L48, NB48, seed=0) if real
+           else synth.smooth_orbitals(N48, L48, NB48, seed=0))
+    _shared["psi48"] = psi
+    chunks = [list(range(j, min(j + 4, NB48))) for j in range(0, NB48, 4)]
+    W = np.empty(psi.shape, dtype=np.complex128)
+    with mp.get_context("fork").Pool(workers) as pool:
+        for cols, Wc in pool.imap_unordered(_w_columns48, chunks):
+            W[cols] = Wc
+    if real:
+        assert np.linalg.norm(W.imag) <= 1e-12 * np.linalg.norm(W.real)
+        W = np.ascontiguousarray(W.real)
+    print(f"full48: W done ({time.time() - t0:.0f} s)", flush=True)
+    g = O.Grid.cubic(N48, L48)
+    M, L, xi = O.compress(psi, W, g)
+    if real:
+        assert np.linalg.norm(np.imag(M)) <= 1e-12 * np.linalg.norm(M)
+        xi = np.real(xi)
+    out = {
+        "case": "48^3 grid, cubic L=20.5 bohr, 80 smooth orthonormal " +
+                ("real " if real else "") + "orbitals (Ecut 10 Ha, "
+                "seed 0); occupied = first 64; Coulomb kernel, g0 = 0",
+        "n": N48, "L": L48, "n_band": NB48, "n_occ": NOCC48,
+        "E_X_trace": O.exchange_energy_trace(M, NOCC48),
+        "E_X_ace": O.exchange_energy_ace(psi[:NOCC48], xi, g),
+        "eig_minus_M": [float(v) for v in np.linalg.eigvalsh(-M)],
+        "M_diag": [float(v) for v in np.real(np.diag(M))],
+        "W_col_norm": [float(v) for v in np.sqrt(g.dV) * np.linalg.norm(W.reshape(NB48, -1), axis=1)],
+        "xi_col_norm": [float(v) for v in
+                        np.sqrt(g.dV) * np.linalg.norm(xi.reshape(NB48, -1), axis=1)],
+    }
+    for name, arr, seed in (("W_samples", W, 11), ("xi_samples", xi, 12)):
+        b, r = _samples(psi.shape, 64, seed)
+        f = arr.reshape(NB48, -1)
+        out[name] = {"band": b, "point": r, "re": [float(f[i, k].real) for i, k in zip(b, r)],
+                     "im": [float(f[i, k].imag) for i, k in zip(b, r)]}
+    name = "smooth48r_full_seed0.json" if real else "smooth48_full_seed0.json"
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(f"full48: done ({time.time() - t0:.0f} s)", flush=True)
+
+
 def full64():
     """64^3, L = 27 bohr, 128 smooth orbitals (seed 0): exchange energy of all 128."""
     psi = synth.smooth_orbitals(64, 27.0, 128, seed=0)
@@ -144,9 +203,12 @@ def full64():
 
 
 def main():
-    which = sys.argv[1:] or ["small", "full64", "full72"]
+    which = sys.argv[1:] or ["small", "full48", "full64", "full72"]
     if "small" in which:
         small()
+    if "full48" in which:
+        full48(int(os.environ.get("GOLDEN_WORKERS", "6")))
+        full48(int(os.environ.get("GOLDEN_WORKERS", "6")), real=True)
     if "full64" in which:
         full64()
     if "full72" in which:
