@@ -189,6 +189,8 @@ def main():
                     help="form of the accumulate pass (0 = library default)")
     ap.add_argument("--batch-form", type=int, default=0, choices=[0, 1, 2],
                     help="cfg4: W stage of the batched build (1 launches, 2 persistent)")
+    ap.add_argument("--branches", type=int, default=4,
+                    help="cfg4: concurrent branch streams of the launches form (1..16)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="cfg4: skip the autotuner (library defaults)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -606,7 +608,7 @@ def run_batched(args, cfg):
         fft_bytes += (3 * tr + p) * g.ng * 8
     del orbs
     ctx = ace.Context(0)
-    nbr = 4
+    nbr = args.branches
     tuned = {}
     if not args.no_autotune:
         # pair-batch width, band block and FFT line shape per grid size, tuned
