@@ -732,10 +732,18 @@ def run_autograd(args, cfg):
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "algorithmic_bytes_per_launch": round(units[dom] * ng * 8 * ppl),
                 "avg_launch_ms": round(avg_ms, 4), "pairs_per_launch": ppl}
+    roofline["traffic"] = measured_traffic(args.workload, dom, ppl)
     extra = {"forward_pairs": fwd_pairs, "backward_pairs": bwd_pairs,
              "profiled_ms_per_step": round(ms_prof, 4),
              "per_kernel": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 5)}
                             for k, v in prof.items()}}
+    if args.copy_probe:
+        # a plain copy of known size, for the scaling of the HBM counters
+        src = torch.zeros(256 * 1024 * 1024 // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        extra["copy_probe_bytes"] = 2 * src.numel() * 8
     config = {"workload": f"cfg5: {cfg['desc']}", "precision": "fp32", "grid": n, "L_bohr": L,
               "n_occ": nocc, "solves_per_step": solves, "parallelism": "single GPU"}
     out = _base_record(args, cfg, "pair Poisson solves/s (E_X forward + backward)",
