@@ -350,10 +350,20 @@ def main():
     # plus the rectangle of extra bands; the accumulate pass reads every pair
     sym = ctx.get_tuning("symmetry") == 1
     if real:
-        # real orbitals: units of two pairs (orbitals 2m, 2m+1) for every band
-        transformed = (nocc + 1) // 2 * nband
+        # real orbitals: units of two pairs.  With the i <-> j symmetry and an
+        # even n_occ (one chunk) the occupied triangle is packed by column
+        # (column c holds floor(c / 2) + 1 units), then (orbital pair, extra
+        # band) units; the accumulate pass serves band pairs (2g, 2g + 1) of the
+        # occupied block from one read of each unit of later columns.  Without
+        # it: (orbital pair, band) units for every band.
+        half = (nocc + 1) // 2
+        if sym and nocc % 2 == 0:
+            transformed = sum(c // 2 + 1 for c in range(nocc)) + (nband - nocc) * half
+            accum_reads = (nocc // 2) * nocc + (nband - nocc) * half
+        else:
+            transformed = accum_reads = half * nband
         per_step = {"pair_fwd_real": transformed, "plane_kernel": transformed,
-                    "pencil_accum_real": transformed}
+                    "pencil_accum_real": accum_reads}
     else:
         transformed = (nocc * (nocc + 1) // 2 + nocc * (nband - nocc)) if sym else pairs
         per_step = {"pair_fwd_slab": transformed, "plane_kernel": transformed,
@@ -371,7 +381,8 @@ def main():
                 "algorithmic_bytes_per_launch": round(bytes_per_pair * pairs_per_launch),
                 "avg_launch_ms": round(avg_ms, 4), "pairs_per_launch": pairs_per_launch}
     build_ms = st_ms["build_W"]
-    build_bytes = (3 * transformed + per_step.get("pencil_accum", transformed)) * ng * sbytes
+    build_bytes = (3 * transformed + per_step.get("pencil_accum", per_step.get(
+        "pencil_accum_real", transformed))) * ng * sbytes
     extra = {
         "profiled_ms_per_step": round(wall_prof * 1e3 / args.steps, 4),
         "stage_ms": {k: round(v, 4) for k, v in st_ms.items()},
