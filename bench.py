@@ -196,8 +196,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of known size (for counter scaling)")
     ap.add_argument("--no-others", action="store_true",
-                    help="the default cfg2 run with its CPU baseline also times cfg2r, cfg3, "
-                         "cfg4 and cfg5 for a few steps each (child processes, after the timed "
+                    help="the default cfg2 run with its CPU baseline also times cfg1, cfg2r, "
+                         "cfg3, cfg4 and cfg5 for a few steps each (child processes, after the timed "
                          "region) and reports them under extra.other_workloads; this skips them")
     args = ap.parse_args()
 
@@ -487,7 +487,7 @@ def other_workloads(args):
     import subprocess
     res = {}
     steps, warmup = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
-    for w in ("cfg2r", "cfg3", "cfg4", "cfg5"):
+    for w in ("cfg1", "cfg2r", "cfg3", "cfg4", "cfg5"):
         log(f"bench: other workload {w} ({steps} steps)")
         cmd = [sys.executable, os.path.abspath(__file__), "--workload", w, "--steps", str(steps),
                "--warmup", str(warmup), "--no-cpu", "--no-others"]
